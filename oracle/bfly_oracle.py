@@ -1,0 +1,292 @@
+"""FP64 CPU oracle for butterfly filtering -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this module.
+The GPU library never calls it and shares no code with it.
+
+It computes, plainly and slowly, what the butterfly-filtering search computes (van Putten,
+"GPU-accelerated broadband analysis of multi-messenger light curves of GRBs", Sec. 2):
+
+* a bank of 1 s chirp templates over an (f0, fdot) grid covering ascending and descending
+  chirps (Sec. 2.1; abstract);
+* matched filtering of a series against every template at every time offset (Sec. 2.1),
+  normalised per window to a correlation coefficient rho;
+* the butterfly output: per offset, max |rho| over the bank and the template reaching it,
+  whose maxima are histogrammed beside a time-randomised control (Fig. 2 caption; Sec. 2.2);
+* the chirp-based spectrogram: per offset and f0 bin, max |rho| over the fdot templates of
+  that bin, and its time average, the broadband spectrum (Sec. 2.1; Fig. 1 caption).
+
+The paper gives no formula for the template, the normalisation, the grid, the spectrogram or
+the tie rule.  The readings used (one chirp per template with phase f0 t + fdot t^2/2 from the
+template start, zero-mean unit-norm templates, centred window norm, inclusive f0-major
+linspace grid, f0 grid index as the spectrogram frequency key, lowest index on ties,
+degenerate-window rule) are listed with their reasons in the design notes; each function
+below names the reading it applies.
+
+Everything is float64.  The correlation numerator is a plain matrix product of the template
+matrix with the window (Hankel) matrix; the window energy is a two-pass centred sum per
+window (no prefix sums), so it is independent of how the GPU computes it.
+
+Parity status: every function here is pinned by the CPU tests (brute force, library
+routines, closed forms, invariants); none is "parity unpinned".
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+DEGENERATE_REL = 1e-12  # a window is degenerate when E <= DEGENERATE_REL * R (reading 13)
+
+
+# ---------------------------------------------------------------------------------------
+# O1: the grid.
+# ---------------------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Grid:
+    f0: np.ndarray        # [K] start frequency of template k (Hz)
+    fdot: np.ndarray      # [K] frequency slope of template k (Hz/s)
+    bin: np.ndarray       # [K] spectrogram bin = local f0 index
+    k_global: np.ndarray  # [K] index in the unsharded f0-major bank
+    n_bins: int
+    n_fdot: int
+
+
+def grid(p) -> Grid:
+    """The (f0, fdot) template grid of bank parameters ``p`` (reading 5: inclusive linspace,
+    f0-major, k = i*n_fdot + j; a shard owns a contiguous f0 index range)."""
+    f0_axis = np.linspace(p.f0_min, p.f0_max, p.n_f0)
+    fd_axis = np.linspace(p.fdot_min, p.fdot_max, p.n_fdot)
+    lo = p.shard_index * p.n_f0 // p.shard_count
+    hi = (p.shard_index + 1) * p.n_f0 // p.shard_count
+    nb = hi - lo
+    f0 = np.repeat(f0_axis[lo:hi], p.n_fdot)
+    fdot = np.tile(fd_axis, nb)
+    b = np.repeat(np.arange(nb), p.n_fdot)
+    kg = lo * p.n_fdot + np.arange(nb * p.n_fdot)
+    return Grid(f0=f0, fdot=fdot, bin=b, k_global=kg, n_bins=nb, n_fdot=p.n_fdot)
+
+
+# ---------------------------------------------------------------------------------------
+# O2: templates.
+# ---------------------------------------------------------------------------------------
+def templates(fs: float, L: int, f0: np.ndarray, fdot: np.ndarray) -> np.ndarray:
+    """Zero-mean, unit-L2-norm chirp templates, float64 [K, L] (Sec. 2.1; readings 1, 2).
+
+    Template k samples cos(2 pi phi) at t_n = n/fs, n = 0..L-1, with phi = f0 t + fdot t^2/2
+    (phase zero at the template start; rectangular window).  The phase is reduced mod 1
+    before the cosine.  The mean over the L samples is removed and the result scaled to
+    unit norm.  A template whose centred norm vanishes cannot be normalised and is rejected.
+    """
+    f0 = np.asarray(f0, dtype=np.float64).reshape(-1, 1)
+    fdot = np.asarray(fdot, dtype=np.float64).reshape(-1, 1)
+    t = np.arange(L, dtype=np.float64) / fs
+    phi = f0 * t + 0.5 * fdot * (t * t)
+    phi = phi - np.floor(phi)
+    c = np.cos(2.0 * np.pi * phi)
+    c = c - c.mean(axis=1, keepdims=True)
+    nrm = np.sqrt((c * c).sum(axis=1, keepdims=True))
+    if np.any(nrm <= 1e-9 * math.sqrt(L)):
+        raise ValueError("degenerate template: zero centred norm")
+    return c / nrm
+
+
+def bank_templates(p, k_lo: int = 0, k_hi: int | None = None) -> np.ndarray:
+    """Templates of the (local) bank index range [k_lo, k_hi) of parameters ``p``."""
+    g = grid(p)
+    k_hi = g.f0.shape[0] if k_hi is None else k_hi
+    return templates(p.fs, p.L, g.f0[k_lo:k_hi], g.fdot[k_lo:k_hi])
+
+
+# ---------------------------------------------------------------------------------------
+# O3: correlation numerator.
+# ---------------------------------------------------------------------------------------
+def windows(x: np.ndarray, L: int, offsets: np.ndarray | None = None) -> np.ndarray:
+    """The Hankel window matrix X[tau, n] = x[tau + n], float64 [len(offsets), L]."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.shape[0] < L:
+        raise ValueError("series shorter than the template")
+    v = sliding_window_view(x, L)
+    return v if offsets is None else v[np.asarray(offsets)]
+
+
+def numerator(x: np.ndarray, H: np.ndarray, offsets: np.ndarray | None = None) -> np.ndarray:
+    """d[tau, k] = sum_n H[k, n] x[tau + n] (matched filtering, Sec. 2.1), float64."""
+    Xw = windows(x, H.shape[1], offsets)
+    return Xw @ H.T
+
+
+def numerator_fft(x: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """The same numerator for one template through zero-padded FFTs (Sec. 2.2 computes the
+    correlations with the FFT).  Linear correlation: size >= N + L - 1.  Returns d[W]."""
+    x = np.asarray(x, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    n, L = x.shape[0], h.shape[0]
+    size = 1 << int(math.ceil(math.log2(n + L - 1)))
+    X = np.fft.rfft(x, size)
+    Hf = np.fft.rfft(h, size)
+    full = np.fft.irfft(X * np.conj(Hf), size)
+    return full[: n - L + 1]
+
+
+# ---------------------------------------------------------------------------------------
+# O4, O5: window energies and degenerate windows.
+# ---------------------------------------------------------------------------------------
+def window_energy(x: np.ndarray, L: int, offsets: np.ndarray | None = None,
+                  norm: str = "centred") -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Per-window energy E, raw energy R and the degenerate flag (readings 3 and 13).
+
+    Centred (default): E = sum_n (x[tau+n] - mean_tau)^2, two passes per window.
+    Raw: E = R = sum_n x[tau+n]^2.
+    Degenerate: R == 0, or E <= 1e-12 * R, or the window holds a non-finite value.
+    """
+    Xw = windows(x, L, offsets)
+    finite = np.all(np.isfinite(Xw), axis=1)
+    Xf = np.where(np.isfinite(Xw), Xw, 0.0)
+    R = (Xf * Xf).sum(axis=1)
+    if norm == "centred":
+        mu = Xf.sum(axis=1, keepdims=True) / L
+        dev = Xf - mu
+        E = (dev * dev).sum(axis=1)
+    elif norm == "raw":
+        E = R.copy()
+    else:
+        raise ValueError(norm)
+    degen = (~finite) | (R == 0.0) | (E <= DEGENERATE_REL * R)
+    return E, R, degen
+
+
+# ---------------------------------------------------------------------------------------
+# O6-O9: correlation coefficient, butterfly output, spectrogram, histogram.
+# ---------------------------------------------------------------------------------------
+def rho(x: np.ndarray, H: np.ndarray, offsets: np.ndarray | None = None,
+        norm: str = "centred") -> tuple[np.ndarray, np.ndarray]:
+    """rho[tau, k] = d[tau, k] / sqrt(E_tau); rows of degenerate windows are 0 (reading 13).
+    Returns (rho, degenerate)."""
+    E, _, degen = window_energy(x, H.shape[1], offsets, norm)
+    Xw = windows(x, H.shape[1], offsets)
+    Xw = np.where(np.isfinite(Xw), Xw, 0.0)
+    d = Xw @ H.T
+    r = np.zeros_like(d)
+    ok = ~degen
+    r[ok] = d[ok] / np.sqrt(E[ok])[:, None]
+    return r, degen
+
+
+def hist_bin(v: np.ndarray, bins: int, lo: float, hi: float) -> np.ndarray:
+    """Bin index min(B-1, max(0, floor((v - lo)/(hi - lo) * B))) (reading 11)."""
+    q = np.floor((np.asarray(v, dtype=np.float64) - lo) / (hi - lo) * bins)
+    return np.clip(q, 0, bins - 1).astype(np.int64)
+
+
+def histogram(m: np.ndarray, degen: np.ndarray, bins: int = 256, lo: float = 0.0,
+              hi: float = 1.0) -> np.ndarray:
+    """Histogram of the butterfly maxima over non-degenerate offsets (Fig. 2 caption)."""
+    b = hist_bin(m[~degen], bins, lo, hi)
+    return np.bincount(b, minlength=bins).astype(np.int64)
+
+
+def decimate(S: np.ndarray, t_block: int) -> np.ndarray:
+    """Row-block maximum of a spectrogram: out[r, i] = max over tau in block r of S[tau, i]."""
+    W = S.shape[0]
+    nr = -(-W // t_block)
+    out = np.zeros((nr, S.shape[1]), dtype=S.dtype)
+    for r in range(nr):
+        out[r] = S[r * t_block:(r + 1) * t_block].max(axis=0)
+    return out
+
+
+def search(x: np.ndarray, p, offsets: np.ndarray | None = None, norm: str = "centred",
+           hist_bins: int = 256, hist_lo: float = 0.0, hist_hi: float = 1.0,
+           k_chunk: int | None = None) -> dict:
+    """The whole search on the offsets given (all W offsets when ``offsets`` is None).
+
+    Returns a dict with
+      m[T]        max_k |rho(tau, k)|           (butterfly output; 0 on degenerate windows)
+      a[T]        the smallest global k reaching m (reading 12); -1 on degenerate windows
+      S[T, B]     max over the fdot templates of f0 bin i of |rho|  (chirp spectrogram)
+      degen[T]    degenerate-window flags
+      hist[B_h]   histogram of m over non-degenerate offsets
+      n_degenerate
+      spectrum[B] time mean of S over the offsets given (over all W: the broadband spectrum)
+      offsets[T]
+    Templates are generated and applied in chunks of whole f0 bins to bound memory; the
+    reductions merge chunks in increasing k with strict comparisons, so ties keep the
+    smallest k.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    g = grid(p)
+    L = p.L
+    W = x.shape[0] - L + 1
+    if W < 1:
+        raise ValueError("series shorter than the template")
+    offs = np.arange(W) if offsets is None else np.asarray(offsets, dtype=np.int64)
+    T = offs.shape[0]
+    E, _, degen = window_energy(x, L, offs, norm)
+    Xw = windows(x, L, offs)
+    Xw = np.where(np.isfinite(Xw), Xw, 0.0)
+    scale = np.zeros(T)
+    scale[~degen] = 1.0 / np.sqrt(E[~degen])
+
+    nb, nfd = g.n_bins, g.n_fdot
+    if k_chunk is None:
+        k_chunk = max(nfd, (1 << 22) // max(T, 1) // nfd * nfd)
+    bins_per_chunk = max(1, k_chunk // nfd)
+    m = np.full(T, -1.0)
+    a = np.full(T, -1, dtype=np.int64)
+    S = np.zeros((T, nb))
+    for b0 in range(0, nb, bins_per_chunk):
+        b1 = min(nb, b0 + bins_per_chunk)
+        k0, k1 = b0 * nfd, b1 * nfd
+        H = templates(p.fs, L, g.f0[k0:k1], g.fdot[k0:k1])
+        r = np.abs((Xw @ H.T) * scale[:, None])          # |rho| [T, k1-k0]
+        S[:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)
+        j = np.argmax(r, axis=1)                          # first maximum in this chunk
+        v = r[np.arange(T), j]
+        better = v > m
+        m[better] = v[better]
+        a[better] = g.k_global[k0 + j[better]]
+    m[degen] = 0.0
+    a[degen] = -1
+    S[degen] = 0.0
+    return {
+        "m": m, "a": a, "S": S, "degen": degen,
+        "hist": histogram(m, degen, hist_bins, hist_lo, hist_hi),
+        "n_degenerate": int(degen.sum()),
+        "spectrum": S.mean(axis=0),
+        "offsets": offs,
+    }
+
+
+def average_spectrum(spectra: list[np.ndarray]) -> np.ndarray:
+    """Mean of per-series spectra (Fig. 1 caption: a spectrum averaged over 42 light curves;
+    reading 10: each series contributes its own time mean, uneven lengths are not pooled)."""
+    return np.mean(np.stack(spectra), axis=0)
+
+
+def top2_margin(x: np.ndarray, p, offsets: np.ndarray, norm: str = "centred") -> np.ndarray:
+    """For each offset, max |rho| minus the second-largest |rho| over the bank.  Used to
+    decide where an argmax comparison is meaningful at a given tolerance."""
+    x = np.asarray(x, dtype=np.float64)
+    g = grid(p)
+    offs = np.asarray(offsets, dtype=np.int64)
+    E, _, degen = window_energy(x, p.L, offs, norm)
+    Xw = np.where(np.isfinite(windows(x, p.L, offs)), windows(x, p.L, offs), 0.0)
+    scale = np.zeros(offs.shape[0])
+    scale[~degen] = 1.0 / np.sqrt(E[~degen])
+    best = np.full(offs.shape[0], -1.0)
+    second = np.full(offs.shape[0], -1.0)
+    nfd = g.n_fdot
+    step = max(nfd, (1 << 22) // max(offs.shape[0], 1) // nfd * nfd)
+    K = g.f0.shape[0]
+    for k0 in range(0, K, step):
+        k1 = min(K, k0 + step)
+        H = templates(p.fs, p.L, g.f0[k0:k1], g.fdot[k0:k1])
+        r = np.abs((Xw @ H.T) * scale[:, None])
+        part = -np.sort(-r, axis=1)[:, :2]
+        cand = np.concatenate([best[:, None], second[:, None], part], axis=1)
+        cand = -np.sort(-cand, axis=1)
+        best, second = cand[:, 0], cand[:, 1]
+    return best - second

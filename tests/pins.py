@@ -1,0 +1,326 @@
+"""Pins of the FP64 oracle: checks against closed forms, library routines, brute force and
+invariants that do not come from the oracle itself.
+
+Each ``pin_*`` takes the oracle module as its argument and raises AssertionError on a
+mismatch.  The same pins run against the real oracle (test_oracle_pins.py) and against
+copies of it with planted mistakes (test_oracle_mutants.py), where at least one must fail.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import scipy.signal
+
+from synth import BankParams, time_randomised
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _small_bank(L=32, n_f0=3, n_fdot=4, fs=64.0):
+    return BankParams(fs=fs, L=L, n_f0=n_f0, n_fdot=n_fdot, f0_min=5.0, f0_max=20.0,
+                      fdot_min=-12.0, fdot_max=12.0)
+
+
+# ---------------------------------------------------------------------------------------
+def pin_template_closed_forms(o):
+    """Hand-derived template values (golden file) for ascending, descending and constant-
+    frequency cases whose phases are exact multiples of 1/8."""
+    with open(os.path.join(GOLDEN, "templates_closed_form.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        h = o.templates(c["fs"], c["L"], np.array([c["f0"]]), np.array([c["fdot"]]))[0]
+        if "h" in c:
+            want = np.array(c["h"])
+        elif "h_times_sqrt102" in c:
+            want = np.array(c["h_times_sqrt102"]) / math.sqrt(102.0)
+        else:
+            r = 1.0 / math.sqrt(2.0)
+            want = np.array([1 - r / 2, r / 2, -1 - r / 2, r / 2] * 2) / math.sqrt(5.0)
+        assert np.allclose(h, want, rtol=0, atol=1e-13), (c, h, want)
+
+
+def pin_template_norms(o):
+    """Every template of a random grid has mean 0 and L2 norm 1 (closed forms)."""
+    rng = np.random.default_rng(11)
+    f0 = rng.uniform(1, 200, 50)
+    fd = rng.uniform(-300, 300, 50)
+    H = o.templates(512.0, 300, f0, fd)
+    assert np.abs(H.mean(axis=1)).max() < 1e-15
+    assert np.abs(np.linalg.norm(H, axis=1) - 1).max() < 1e-14
+
+
+def pin_grid(o):
+    """Grid: inclusive linspace endpoints and steps, f0-major order, bins, shard ranges and
+    the paper's 8.64M bank total (golden file) split into 12 shares of 720,000."""
+    p = BankParams(fs=512.0, L=512, n_f0=16, n_fdot=16, f0_min=20.0, f0_max=200.0,
+                   fdot_min=-100.0, fdot_max=100.0)
+    g = o.grid(p)
+    assert g.f0.shape[0] == 256
+    assert g.f0[0] == 20.0 and g.f0[-1] == 200.0
+    assert g.fdot[0] == -100.0 and g.fdot[15] == 100.0
+    assert abs(g.f0[16] - 32.0) < 1e-12           # f0 step (200-20)/15 = 12, f0-major
+    assert abs(g.fdot[1] - (-100.0 + 200.0 / 15.0)) < 1e-12
+    assert np.all(g.f0[:16] == 20.0)
+    assert list(g.bin[:33:16]) == [0, 1, 2]
+    with open(os.path.join(GOLDEN, "bank_sizes.json")) as f:
+        gold = json.load(f)
+    total = 0
+    for s in range(gold["n_gpus"]):
+        q = BankParams(fs=2000.0, L=16, n_f0=gold["n_f0"], n_fdot=gold["n_fdot"],
+                       f0_min=10.0, f0_max=1000.0, fdot_min=-1000.0, fdot_max=1000.0,
+                       shard_index=s, shard_count=gold["n_gpus"])
+        gq = o.grid(q)
+        if s == 0:
+            assert gq.f0.shape[0] == gold["share_templates"]
+            assert gq.n_bins == gold["share_bins"]
+            assert gq.k_global[0] == 0
+        if s == 1:
+            assert gq.k_global[0] == gold["share_templates"]
+            assert gq.f0[0] == np.linspace(10.0, 1000.0, 2880)[240]
+        total += gq.f0.shape[0]
+    assert total == gold["total_templates"]
+
+
+def _brute_search(x, p, norm="centred", hist_bins=8):
+    """Pure-Python loops: templates, correlation, window energy, rho and all reductions."""
+    L = p.L
+    f0s = [p.f0_min + i * (p.f0_max - p.f0_min) / (p.n_f0 - 1) for i in range(p.n_f0)]
+    f0s[-1] = p.f0_max
+    fds = [p.fdot_min + j * (p.fdot_max - p.fdot_min) / (p.n_fdot - 1) for j in range(p.n_fdot)]
+    fds[-1] = p.fdot_max
+    H = []
+    for i in range(p.n_f0):
+        for j in range(p.n_fdot):
+            c = []
+            for n in range(L):
+                t = n / p.fs
+                c.append(math.cos(2 * math.pi * (f0s[i] * t + 0.5 * fds[j] * t * t)))
+            mu = sum(c) / L
+            c = [v - mu for v in c]
+            nr = math.sqrt(sum(v * v for v in c))
+            H.append([v / nr for v in c])
+    W = len(x) - L + 1
+    out_m, out_a, out_S, out_deg = [], [], [], []
+    for tau in range(W):
+        win = [float(x[tau + n]) for n in range(L)]
+        bad = any(not math.isfinite(v) for v in win)
+        win = [v if math.isfinite(v) else 0.0 for v in win]
+        R = sum(v * v for v in win)
+        if norm == "centred":
+            mu = sum(win) / L
+            E = sum((v - mu) ** 2 for v in win)
+        else:
+            E = R
+        deg = bad or R == 0.0 or E <= 1e-12 * R
+        out_deg.append(deg)
+        if deg:
+            out_m.append(0.0)
+            out_a.append(-1)
+            out_S.append([0.0] * p.n_f0)
+            continue
+        best, arg = -1.0, -1
+        S = [0.0] * p.n_f0
+        for k in range(len(H)):
+            d = 0.0
+            for n in range(L):
+                d += H[k][n] * win[n]
+            r = abs(d) / math.sqrt(E)
+            if r > best:
+                best, arg = r, k
+            b = k // p.n_fdot
+            S[b] = max(S[b], r)
+        out_m.append(best)
+        out_a.append(arg)
+        out_S.append(S)
+    hist = [0] * hist_bins
+    for m, deg in zip(out_m, out_deg):
+        if not deg:
+            b = int(math.floor(m * hist_bins))
+            hist[min(hist_bins - 1, max(0, b))] += 1
+    return (np.array(out_m), np.array(out_a), np.array(out_S), np.array(out_deg),
+            np.array(hist))
+
+
+def pin_brute_force(o):
+    """Tiny inputs (N <= 64, L <= 8, K <= 6) against pure-Python loops, including a constant
+    (degenerate) window, a NaN, and the raw norm."""
+    p = BankParams(fs=16.0, L=7, n_f0=2, n_fdot=3, f0_min=1.5, f0_max=4.0,
+                   fdot_min=-3.0, fdot_max=5.0)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(40)
+    x[20:28] = 0.7            # constant run: windows 20, 21 are degenerate
+    x[33] = np.nan            # windows 27..33 hold a NaN
+    for norm in ("centred", "raw"):
+        m, a, S, deg, hist = _brute_search(x, p, norm, hist_bins=8)
+        r = o.search(x, p, norm=norm, hist_bins=8)
+        assert np.array_equal(r["degen"], deg)
+        assert np.allclose(r["m"], m, rtol=0, atol=1e-13)
+        assert np.array_equal(r["a"], a)
+        assert np.allclose(r["S"], S, rtol=0, atol=1e-13)
+        assert np.array_equal(r["hist"], hist)
+        assert r["n_degenerate"] == int(deg.sum())
+
+
+def pin_np_correlate(o):
+    """The numerator equals numpy.correlate(x, h, 'valid') for each template."""
+    p = _small_bank()
+    H = o.bank_templates(p)
+    x = np.random.default_rng(6).standard_normal(300)
+    d = o.numerator(x, H)
+    for k in range(H.shape[0]):
+        ref = np.correlate(x, H[k], mode="valid")
+        assert np.allclose(d[:, k], ref, rtol=0, atol=1e-12)
+
+
+def pin_fft_agreement(o):
+    """Direct correlation equals FFT correlation (scipy, an independent library) to 1e-12
+    of the window norm; the oracle's own FFT path agrees too."""
+    p = _small_bank(L=64)
+    H = o.bank_templates(p)
+    x = np.random.default_rng(7).standard_normal(1000) * 3.0 + 1.0
+    d = o.numerator(x, H)
+    _, R, _ = o.window_energy(x, p.L)
+    for k in range(H.shape[0]):
+        ref = scipy.signal.correlate(x, H[k], mode="valid", method="fft")
+        assert np.all(np.abs(d[:, k] - ref) <= 1e-12 * np.sqrt(R) + 1e-13)
+        own = o.numerator_fft(x, H[k])
+        assert np.all(np.abs(d[:, k] - own) <= 1e-12 * np.sqrt(R) + 1e-13)
+
+
+def pin_self_correlation(o):
+    """A series holding template k at offset s (zeros elsewhere) gives rho(s, k) = 1, the
+    butterfly output 1 at (s, k), and all-zero windows are degenerate."""
+    p = _small_bank(L=40)
+    H = o.bank_templates(p)
+    for k in (0, 5, H.shape[0] - 1):
+        s = 97
+        x = np.zeros(300)
+        x[s:s + p.L] = H[k]
+        r = o.search(x, p)
+        i = s
+        assert abs(r["m"][i] - 1.0) < 1e-14
+        assert r["a"][i] == k
+        assert r["degen"][s + p.L:].all() and r["degen"][: s - p.L + 1].all()
+        assert not r["degen"][s]
+
+
+def pin_cauchy_schwarz(o):
+    """|rho| <= 1 on arbitrary data (Cauchy-Schwarz with a zero-mean unit-norm template)."""
+    p = _small_bank(L=24)
+    x = np.random.default_rng(8).standard_cauchy(500)
+    r = o.search(x, p)
+    assert np.all(r["m"] <= 1.0 + 1e-12)
+    assert np.all(r["S"] <= 1.0 + 1e-12)
+
+
+def pin_invariants(o):
+    """Centred rho is invariant to affine maps of x up to sign; rho(-x) = -rho(x); a shift
+    of x shifts every output."""
+    p = _small_bank(L=32)
+    H = o.bank_templates(p)
+    x = np.random.default_rng(9).standard_normal(400)
+    r1, _ = o.rho(x, H)
+    r2, _ = o.rho(3.5 * x - 7.25, H)
+    r3, _ = o.rho(-x, H)
+    assert np.allclose(r2, r1, rtol=0, atol=1e-12)
+    assert np.allclose(r3, -r1, rtol=0, atol=1e-12)
+    a = o.search(x, p)
+    b = o.search(x[13:], p)
+    assert np.allclose(b["m"], a["m"][13:], rtol=0, atol=1e-13)
+    assert np.array_equal(b["a"], a["a"][13:])
+
+
+def pin_noise_statistic(o):
+    """For iid Gaussian data, E[rho^2] = 1/(L-1) for the centred norm (x - mean is uniform
+    on the sphere of the complement of the constant vector, which holds h) and 1/L for the
+    raw norm.  Checked on 6000 independent windows (statistical error about 2%)."""
+    L = 48
+    p = BankParams(fs=64.0, L=L, n_f0=1, n_fdot=2, f0_min=9.0, f0_max=9.0,
+                   fdot_min=-20.0, fdot_max=20.0)
+    H = o.bank_templates(p)
+    x = np.random.default_rng(10).standard_normal(6000 * L)
+    offs = np.arange(0, 6000 * L - L + 1, L)
+    for norm, want in (("centred", 1.0 / (L - 1)), ("raw", 1.0 / L)):
+        r, _ = o.rho(x, H, offs, norm)
+        est = float((r[:, 0] ** 2).mean())
+        assert abs(est / want - 1.0) < 0.08, (norm, est, want)
+
+
+def pin_recovery(o):
+    """An on-grid chirp (a bank template's waveform, amplitude 0.5) injected at an integer
+    start into unit noise is recovered at exactly that offset and template."""
+    p = BankParams(fs=512.0, L=512, n_f0=16, n_fdot=16, f0_min=20.0, f0_max=200.0,
+                   fdot_min=-100.0, fdot_max=100.0)
+    g = o.grid(p)
+    k = 3 * 16 + 11                       # f0 = 56 Hz, fdot = +46.67 Hz/s
+    t = np.arange(512) / 512.0
+    chirp = np.cos(2 * np.pi * (g.f0[k] * t + 0.5 * g.fdot[k] * t * t))
+    for seed in (1, 2, 3):
+        x = np.random.default_rng(seed).standard_normal(2048)
+        x[666:666 + 512] += 0.5 * chirp
+        r = o.search(x, p, offsets=np.arange(500, 900))
+        i = int(np.argmax(r["m"]))
+        assert r["offsets"][i] == 666 and r["a"][i] == k, (seed, r["offsets"][i], r["a"][i])
+
+
+def pin_spectrogram_histogram(o):
+    """max_i S[tau, i] = m[tau]; decimated rows are row-block maxima; the histogram sums to
+    W - n_degenerate; the spectrum is the time mean of S; bin edges follow the floor rule."""
+    p = _small_bank(L=16)
+    x = np.random.default_rng(12).standard_normal(300)
+    x[100:130] = 2.0
+    r = o.search(x, p, hist_bins=16)
+    assert np.allclose(r["S"].max(axis=1), r["m"], rtol=0, atol=0)
+    W = x.shape[0] - p.L + 1
+    assert int(r["hist"].sum()) == W - r["n_degenerate"] and r["n_degenerate"] > 0
+    Sd = o.decimate(r["S"], 7)
+    assert Sd.shape == (-(-W // 7), p.n_f0)
+    assert np.array_equal(Sd[3], r["S"][21:28].max(axis=0))
+    assert np.allclose(r["spectrum"] * W, r["S"].sum(axis=0), rtol=1e-14, atol=0)
+    b = o.hist_bin(np.array([-0.1, 0.0, 1 / 256, 0.5 - 1e-12, 0.5, 0.999, 1.0, 7.0]), 256, 0.0, 1.0)
+    assert list(b) == [0, 0, 1, 127, 128, 255, 255, 255]
+    # per-bin rows: bin i of the spectrogram only sees templates i*n_fdot .. i*n_fdot+n_fdot-1
+    H = o.bank_templates(p)
+    rr, _ = o.rho(x, H)
+    want = np.abs(rr).reshape(W, p.n_f0, p.n_fdot).max(axis=2)
+    assert np.allclose(r["S"], want, rtol=0, atol=1e-13)
+
+
+def pin_degenerate_rule(o):
+    """Constant, all-zero and NaN windows are degenerate; a tiny non-constant one is not."""
+    L = 8
+    x = np.concatenate([np.full(8, 3.0), np.zeros(8), [1.0, np.nan] + [0.5] * 6,
+                        1e-150 * np.arange(8.0)])
+    E, R, deg = o.window_energy(x, L, np.array([0, 8, 16, 24]))
+    assert list(deg) == [True, True, True, False]
+
+
+def pin_ties(o):
+    """Identical templates tie exactly: the smallest index wins, also across template chunks
+    (a grid whose fdot axis collapses to one value repeats each f0 template n_fdot times)."""
+    p = BankParams(fs=64.0, L=20, n_f0=3, n_fdot=3, f0_min=4.0, f0_max=9.0,
+                   fdot_min=2.0, fdot_max=2.0)
+    x = np.random.default_rng(14).standard_normal(200)
+    for kc in (3, 9):
+        r = o.search(x, p, k_chunk=kc)
+        assert np.all(r["a"] % 3 == 0), r["a"][:20]
+    q = BankParams(fs=64.0, L=20, n_f0=2, n_fdot=3, f0_min=6.0, f0_max=6.0,
+                   fdot_min=1.0, fdot_max=1.0)
+    for kc in (3, 6):
+        r = o.search(x, q, k_chunk=kc)
+        assert np.all(r["a"] == 0)
+
+
+def pin_control(o):
+    """Time randomisation keeps the value multiset (the histogram) and reorders samples."""
+    x = np.random.default_rng(13).standard_normal(1000)
+    xc = time_randomised(x, seed=103)
+    assert np.array_equal(np.sort(xc), np.sort(x))
+    assert not np.array_equal(xc, x)
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -1,0 +1,72 @@
+"""Planted mistakes in a copy of the oracle must each fail at least one pin.
+
+Each mutant replaces one snippet of the oracle's source (a dropped term, a wrong sign or
+index, a transposed operand, a wrong reduction) and is executed as a separate module; the
+real oracle is untouched.  A snippet that no longer exists fails the test loudly.
+"""
+import os
+import sys
+import types
+
+import pytest
+
+from tests.pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "bfly_oracle.py")
+
+MUTANTS = {
+    "no_mean_removal": ("c = c - c.mean(axis=1, keepdims=True)", "c = c"),
+    "dropped_half": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t + fdot * (t * t)"),
+    "fdot_sign": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t - 0.5 * fdot * (t * t)"),
+    "t_in_samples": ("t = np.arange(L, dtype=np.float64) / fs", "t = np.arange(L, dtype=np.float64)"),
+    "convolution": ("r = np.abs((Xw @ H.T) * scale[:, None])          # |rho|",
+                    "r = np.abs((Xw[:, ::-1] @ H.T) * scale[:, None])          # |rho|"),
+    "numerator_flip": ("    return Xw @ H.T\n", "    return Xw @ H[:, ::-1].T\n"),
+    "raw_energy": ("dev = Xf - mu", "dev = Xf"),
+    "norm_not_sqrt": ("scale[~degen] = 1.0 / np.sqrt(E[~degen])\n\n    nb",
+                      "scale[~degen] = 1.0 / E[~degen]\n\n    nb"),
+    "argmax_last": ("j = np.argmax(r, axis=1)                          # first",
+                    "j = r.shape[1] - 1 - np.argmax(r[:, ::-1], axis=1)  # first"),
+    "merge_ge": ("better = v > m", "better = v >= m"),
+    "fdot_major": ("f0 = np.repeat(f0_axis[lo:hi], p.n_fdot)\n    fdot = np.tile(fd_axis, nb)",
+                   "f0 = np.tile(f0_axis[lo:hi], p.n_fdot)\n    fdot = np.repeat(fd_axis, nb)"),
+    "linspace_open": ("fd_axis = np.linspace(p.fdot_min, p.fdot_max, p.n_fdot)",
+                      "fd_axis = np.linspace(p.fdot_min, p.fdot_max, p.n_fdot, endpoint=False)"),
+    "shard_index": ("kg = lo * p.n_fdot + np.arange(nb * p.n_fdot)", "kg = np.arange(nb * p.n_fdot)"),
+    "hist_round": ("q = np.floor(", "q = np.round("),
+    "hist_with_degenerate": ("b = hist_bin(m[~degen], bins, lo, hi)", "b = hist_bin(m, bins, lo, hi)"),
+    "spec_transposed": ("S[:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)",
+                        "S[:, b0:b1] = r.reshape(T, nfd, b1 - b0).max(axis=1)"),
+    "nan_not_degenerate": ("degen = (~finite) | (R == 0.0)", "degen = (R == 0.0)"),
+    "no_rel_threshold": ("| (E <= DEGENERATE_REL * R)", "| (E < 0.0)"),
+    "window_shift": ("return v if offsets is None else v[np.asarray(offsets)]",
+                     "return v[1:] if offsets is None else v[np.asarray(offsets) + 1]"),
+    "spectrum_max": ('"spectrum": S.mean(axis=0)', '"spectrum": S.max(axis=0)'),
+}
+
+
+def _load_mutant(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutant {name}: snippet not found in the oracle"
+    mod = types.ModuleType(f"oracle_mutant_{name}")
+    mod.__file__ = SRC
+    sys.modules[mod.__name__] = mod        # dataclasses resolve their module by name
+    try:
+        exec(compile(src.replace(old, new), SRC, "exec"), mod.__dict__)
+    finally:
+        del sys.modules[mod.__name__]
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    old, new = MUTANTS[name]
+    mod = _load_mutant(name, old, new)
+    failed = []
+    for pin in ALL_PINS:
+        try:
+            pin(mod)
+        except Exception as e:  # AssertionError, or the mutant crashing on a pin's input
+            failed.append((pin.__name__, type(e).__name__))
+    assert failed, f"no pin catches mutant {name}"
