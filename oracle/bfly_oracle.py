@@ -290,3 +290,72 @@ def top2_margin(x: np.ndarray, p, offsets: np.ndarray, norm: str = "centred") ->
         cand = -np.sort(-cand, axis=1)
         best, second = cand[:, 0], cand[:, 1]
     return best - second
+
+
+def rho_at(x: np.ndarray, p, offsets: np.ndarray, k_global: np.ndarray,
+           norm: str = "centred") -> np.ndarray:
+    """|rho(tau_i, k_i)| in float64 for given (offset, global template index) pairs; used to
+    check that a reported argmax really reaches the reported maximum.  k_i = -1 gives 0."""
+    x = np.asarray(x, dtype=np.float64)
+    g = grid(p)
+    offs = np.asarray(offsets, dtype=np.int64)
+    kg = np.asarray(k_global, dtype=np.int64)
+    out = np.zeros(offs.shape[0])
+    ok = kg >= 0
+    if not ok.any():
+        return out
+    kl = kg[ok] - int(g.k_global[0])
+    if np.any(kl < 0) or np.any(kl >= g.f0.shape[0]):
+        raise ValueError("template index outside the bank")
+    H = templates(p.fs, p.L, g.f0[kl], g.fdot[kl])
+    E, _, degen = window_energy(x, p.L, offs[ok], norm)
+    Xw = windows(x, p.L, offs[ok])
+    Xw = np.where(np.isfinite(Xw), Xw, 0.0)
+    d = np.einsum("ij,ij->i", Xw, H)
+    r = np.zeros(d.shape[0])
+    r[~degen] = np.abs(d[~degen]) / np.sqrt(E[~degen])
+    out[ok] = r
+    return out
+
+
+def search_many(xs: list, p, offsets_list: list, norm: str = "centred") -> list:
+    """``search`` for several series at once (each on its own offsets), generating every
+    template chunk once.  Returns one dict per series with m, a, S, degen, offsets."""
+    g = grid(p)
+    L = p.L
+    nb, nfd = g.n_bins, g.n_fdot
+    prep = []
+    for x, offs in zip(xs, offsets_list):
+        x = np.asarray(x, dtype=np.float64)
+        offs = np.asarray(offs, dtype=np.int64)
+        E, _, degen = window_energy(x, L, offs, norm)
+        Xw = np.where(np.isfinite(windows(x, L, offs)), windows(x, L, offs), 0.0)
+        scale = np.zeros(offs.shape[0])
+        scale[~degen] = 1.0 / np.sqrt(E[~degen])
+        T = offs.shape[0]
+        prep.append({"Xw": Xw, "scale": scale, "degen": degen, "offsets": offs,
+                     "m": np.full(T, -1.0), "a": np.full(T, -1, dtype=np.int64),
+                     "S": np.zeros((T, nb))})
+    T_all = sum(q["offsets"].shape[0] for q in prep)
+    bins_per_chunk = max(1, (1 << 22) // max(T_all, 1) // nfd)
+    for b0 in range(0, nb, bins_per_chunk):
+        b1 = min(nb, b0 + bins_per_chunk)
+        k0, k1 = b0 * nfd, b1 * nfd
+        H = templates(p.fs, L, g.f0[k0:k1], g.fdot[k0:k1])
+        for q in prep:
+            T = q["offsets"].shape[0]
+            r = np.abs((q["Xw"] @ H.T) * q["scale"][:, None])
+            q["S"][:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)
+            j = np.argmax(r, axis=1)
+            v = r[np.arange(T), j]
+            better = v > q["m"]
+            q["m"][better] = v[better]
+            q["a"][better] = g.k_global[k0 + j[better]]
+    out = []
+    for q in prep:
+        d = q["degen"]
+        q["m"][d] = 0.0
+        q["a"][d] = -1
+        q["S"][d] = 0.0
+        out.append({"m": q["m"], "a": q["a"], "S": q["S"], "degen": d, "offsets": q["offsets"]})
+    return out

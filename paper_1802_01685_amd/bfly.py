@@ -1,0 +1,269 @@
+"""Python binding of libbfly.so (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name (``bf_<name>`` in
+include/bfly.h).  PyTorch provides device memory and the current stream; all arithmetic
+runs in the library's HIP kernels.  A missing or unloadable library raises at import of
+the first call -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfly.so")
+
+BF_OK, BF_EINVAL, BF_ENOMEM, BF_EBUDGET, BF_EAGAIN, BF_ENOTFOUND, BF_EHIP, BF_ECANCELED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp8": 2}
+NORMS = {"centred": 0, "raw": 1}
+STATUS_NAMES = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ENOMEM", -3: "BF_EBUDGET",
+                -4: "BF_EAGAIN", -5: "BF_ENOTFOUND", -6: "BF_EHIP", -7: "BF_ECANCELED"}
+EXPORTED = ["bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy",
+            "bf_workspace_bytes", "bf_search_segment", "bf_search_batch", "bf_plan",
+            "bf_set_timing", "bf_kernel_times", "bf_last_error"]
+
+
+class BflyError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BankDesc(ctypes.Structure):
+    _fields_ = [("fs", ctypes.c_double), ("L", ctypes.c_int32), ("n_f0", ctypes.c_int32),
+                ("n_fdot", ctypes.c_int32), ("shard_index", ctypes.c_int32),
+                ("shard_count", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("f0_min", ctypes.c_double), ("f0_max", ctypes.c_double),
+                ("fdot_min", ctypes.c_double), ("fdot_max", ctypes.c_double)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_int32), ("t_block", ctypes.c_int32),
+                ("hist_bins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hist_lo", ctypes.c_double), ("hist_hi", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("max_abs", ctypes.c_void_p), ("argmax", ctypes.c_void_p),
+                ("spec", ctypes.c_void_p), ("spectrum", ctypes.c_void_p),
+                ("hist", ctypes.c_void_p), ("n_degenerate", ctypes.c_void_p)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", Result)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1802_01685_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, dp = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64,
+                            ctypes.c_void_p)
+    sig = {
+        "bf_bank_bytes": [ctypes.POINTER(BankDesc), ctypes.POINTER(sz)],
+        "bf_bank_create": [ctypes.POINTER(BankDesc), vp, sz, vp, ctypes.POINTER(vp)],
+        "bf_bank_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64), dp, dp],
+        "bf_bank_destroy": [vp],
+        "bf_workspace_bytes": [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(SearchParams),
+                               ctypes.POINTER(sz)],
+        "bf_search_segment": [vp, vp, i64, ctypes.POINTER(SearchParams), ctypes.POINTER(Result),
+                              vp, sz, vp],
+        "bf_search_batch": [vp, ctypes.POINTER(Segment), i32, ctypes.POINTER(SearchParams), vp,
+                            sz, vp],
+        "bf_plan": [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "bf_set_timing": [i32],
+        "bf_kernel_times": [ctypes.POINTER(ctypes.c_double)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.bf_last_error.argtypes = []
+    L.bf_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().bf_last_error().decode()
+
+
+def _check(status: int) -> None:
+    if status != BF_OK:
+        raise BflyError(status, last_error())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def make_desc(p, precision: str = "fp32") -> BankDesc:
+    """A bank descriptor from any object with the grid attributes (fs, L, n_f0, n_fdot,
+    f0_min, f0_max, fdot_min, fdot_max and optionally shard_index, shard_count)."""
+    g = (lambda k, d=None: p.get(k, d)) if isinstance(p, dict) else \
+        (lambda k, d=None: getattr(p, k, d))
+    return BankDesc(fs=float(g("fs")), L=int(g("L")), n_f0=int(g("n_f0")),
+                    n_fdot=int(g("n_fdot")), shard_index=int(g("shard_index", 0)),
+                    shard_count=int(g("shard_count", 1)),
+                    precision=PRECISIONS[precision] if isinstance(precision, str) else precision,
+                    f0_min=float(g("f0_min")), f0_max=float(g("f0_max")),
+                    fdot_min=float(g("fdot_min")), fdot_max=float(g("fdot_max")))
+
+
+def make_params(norm: str = "centred", t_block: int = 1, hist_bins: int = 256,
+                hist_lo: float = 0.0, hist_hi: float = 1.0) -> SearchParams:
+    return SearchParams(norm=NORMS[norm] if isinstance(norm, str) else norm, t_block=t_block,
+                        hist_bins=hist_bins, reserved=0, hist_lo=hist_lo, hist_hi=hist_hi)
+
+
+def bank_bytes(desc: BankDesc) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().bf_bank_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class Bank:
+    """A bank handle plus the torch buffer that holds its device memory."""
+    handle: int
+    memory: torch.Tensor
+    desc: BankDesc
+    K: int
+    n_bins: int
+    k_offset: int
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bf_bank_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+    def grid(self):
+        """(f0[K], fdot[K]) of the bank's templates, float64 numpy arrays."""
+        import numpy as np
+        f0 = np.empty(self.K, dtype=np.float64)
+        fd = np.empty(self.K, dtype=np.float64)
+        _check(lib().bf_bank_info(ctypes.c_void_p(self.handle), None, None, None,
+                                  f0.ctypes.data, fd.ctypes.data))
+        return f0, fd
+
+
+def bank_create(p, precision: str = "fp32", device=None, stream=None) -> Bank:
+    """Allocates the bank's device memory with torch and builds the bank into it."""
+    desc = make_desc(p, precision)
+    nbytes = bank_bytes(desc)
+    mem = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+    h = ctypes.c_void_p()
+    _check(lib().bf_bank_create(ctypes.byref(desc), ctypes.c_void_p(mem.data_ptr()), nbytes,
+                                ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    K, nb, ko = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().bf_bank_info(h, ctypes.byref(K), ctypes.byref(nb), ctypes.byref(ko), None, None))
+    return Bank(handle=h.value, memory=mem, desc=desc, K=K.value, n_bins=nb.value,
+                k_offset=ko.value)
+
+
+def workspace_bytes(bank: Bank, ns, params: SearchParams) -> int:
+    arr = (ctypes.c_int64 * len(ns))(*[int(v) for v in ns])
+    out = ctypes.c_size_t()
+    _check(lib().bf_workspace_bytes(ctypes.c_void_p(bank.handle), arr, len(ns),
+                                    ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def plan(bank: Bank, ns) -> tuple[int, int]:
+    arr = (ctypes.c_int64 * len(ns))(*[int(v) for v in ns])
+    r, items = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().bf_plan(ctypes.c_void_p(bank.handle), arr, len(ns), ctypes.byref(r),
+                         ctypes.byref(items)))
+    return r.value, items.value
+
+
+def alloc_outputs(bank: Bank, n: int, params: SearchParams, device,
+                  want=("max_abs", "argmax", "spec", "spectrum", "hist", "n_degenerate")) -> dict:
+    """torch tensors for the outputs of one series of n samples."""
+    W = n - bank.desc.L + 1
+    rows = -(-W // params.t_block)
+    shapes = {"max_abs": ((W,), torch.float32), "argmax": ((W,), torch.int32),
+              "spec": ((rows, bank.n_bins), torch.float32),
+              "spectrum": ((bank.n_bins,), torch.float64),
+              "hist": ((params.hist_bins,), torch.int32),  # uint32 bit pattern
+              "n_degenerate": ((1,), torch.int64)}
+    return {k: torch.empty(*shapes[k][0], dtype=shapes[k][1], device=device) for k in want}
+
+
+def _result(o: dict) -> Result:
+    return Result(max_abs=_ptr(o.get("max_abs")), argmax=_ptr(o.get("argmax")),
+                  spec=_ptr(o.get("spec")), spectrum=_ptr(o.get("spectrum")),
+                  hist=_ptr(o.get("hist")), n_degenerate=_ptr(o.get("n_degenerate")))
+
+
+def alloc_workspace(bank: Bank, ns, params: SearchParams, device) -> torch.Tensor:
+    return torch.empty(workspace_bytes(bank, ns, params), dtype=torch.uint8, device=device)
+
+
+def search_segment(bank: Bank, x: torch.Tensor, params: SearchParams | None = None,
+                   out: dict | None = None, workspace: torch.Tensor | None = None,
+                   stream=None) -> dict:
+    """Searches one float32 device series; returns the dict of output tensors."""
+    params = params or make_params()
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    n = x.shape[0]
+    out = out if out is not None else alloc_outputs(bank, n, params, x.device)
+    ws = workspace if workspace is not None else alloc_workspace(bank, [n], params, x.device)
+    res = _result(out)
+    _check(lib().bf_search_segment(ctypes.c_void_p(bank.handle), ctypes.c_void_p(x.data_ptr()),
+                                   n, ctypes.byref(params), ctypes.byref(res),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def search_batch(bank: Bank, xs: list, params: SearchParams | None = None,
+                 outs: list | None = None, workspace: torch.Tensor | None = None,
+                 stream=None) -> list:
+    """Searches several float32 device series in one pass; returns their output dicts."""
+    params = params or make_params()
+    ns = [int(x.shape[0]) for x in xs]
+    for x in xs:
+        assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    outs = outs if outs is not None else [alloc_outputs(bank, n, params, x.device)
+                                          for n, x in zip(ns, xs)]
+    ws = workspace if workspace is not None else alloc_workspace(bank, ns, params, xs[0].device)
+    segs = (Segment * len(xs))()
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        segs[i].x = x.data_ptr()
+        segs[i].n = ns[i]
+        segs[i].out = _result(o)
+    _check(lib().bf_search_batch(ctypes.c_void_p(bank.handle), segs, len(xs),
+                                 ctypes.byref(params), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), ctypes.c_void_p(_stream(stream))))
+    return outs
+
+
+def set_timing(enable: bool) -> None:
+    _check(lib().bf_set_timing(1 if enable else 0))
+
+
+def kernel_times() -> dict:
+    """Milliseconds of the calling thread's last timed search, per kernel."""
+    ms = (ctypes.c_double * 5)()
+    _check(lib().bf_kernel_times(ms))
+    return dict(zip(("zero", "prefix", "norms", "main", "finalize"), list(ms)))

@@ -1,0 +1,66 @@
+"""Builds libbfly.so (the HIP kernels and the C-ABI runtime) for gfx950, in-tree.
+
+    python -m paper_1802_01685_amd.build
+
+Compiles csrc/bfly_kernels.hip and csrc/bfly_api.cpp with hipcc and links them into
+paper_1802_01685_amd/libbfly.so next to this file.  Always recompiles.
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libbfly.so")
+
+ARCH = "gfx950"
+COMMON = [
+    "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    "-ffp-contract=off",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+# Packed FP32 arithmetic is kept off in all device code.
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd: list[str]) -> None:
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"build failed ({r.returncode}): {' '.join(cmd)}\n{out}")
+    if out.strip():
+        print(out, file=sys.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    with tempfile.TemporaryDirectory(prefix="bfly_build_") as tmp:
+        k_obj = os.path.join(tmp, "bfly_kernels.o")
+        a_obj = os.path.join(tmp, "bfly_api.o")
+        _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "bfly_kernels.hip"), "-o", k_obj])
+        _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "bfly_api.cpp"), "-o", a_obj])
+        tmp_lib = os.path.join(tmp, "libbfly.so")
+        _run([hipcc, *DEVICE, "-shared", "-fPIC", k_obj, a_obj, "-o", tmp_lib])
+        shutil.copyfile(tmp_lib, LIB + ".tmp")
+        os.replace(LIB + ".tmp", LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

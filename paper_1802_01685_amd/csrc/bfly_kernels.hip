@@ -1,0 +1,759 @@
+// HIP kernels of the butterfly-filtering search, written for gfx950 (MI355X).
+//
+//   k_bank_gen   float64 chirp templates -> quantised bank in the MFMA operand layout
+//   k_zero       clears the running maxima, spectrogram, spectrum sums and histograms
+//   k_prefix     float64 (double-double) prefix sums of x and x^2, non-finite counts
+//   k_norms      per-window energies from the prefix sums -> 1/sqrt(E), degenerate flags
+//   k_main       the template x window contraction on MFMA with the reductions fused in
+//   k_finalize   butterfly output, histogram of maxima, spectrum
+//
+// Matched filtering of a series against a bank of chirps (Sec. 2.1) is, for every offset
+// tau and template k, d(tau,k) = sum_n h_k[n] x[tau+n]: a GEMM with M = templates,
+// N = offsets, K = taps, whose N x K operand is the Hankel matrix X[n][tau] = x[tau+n].
+// k_main keeps a strip of the series in LDS and builds every Hankel operand fragment from
+// it, streams the templates from HBM in a layout that lets each lane load its MFMA operand
+// with 16-byte loads, and never stores d: the per-offset maximum/argmax (the butterfly
+// output, Fig. 2) and the per-f0-bin maximum (the chirp spectrogram, Sec. 2.1) are reduced
+// in registers as each template tile completes.
+#include "bfly_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bfly {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------------------
+// Small numeric helpers.
+// ---------------------------------------------------------------------------------------
+
+// float -> bf16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// double rounded to bf16 precision (8 significant bits), nearest even, kept as a double.
+__device__ __forceinline__ double round_bf16_d(double h) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(h);
+  u = u + ((1ull << 44) - 1ull) + ((u >> 45) & 1ull);
+  u &= ~((1ull << 45) - 1ull);
+  return __longlong_as_double((long long)u);
+}
+
+struct dd {
+  double hi, lo;
+};
+
+// Double-double sum (Knuth two-sum of the leading parts, then renormalised).
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  double s = a.hi + b.hi;
+  double bb = s - a.hi;
+  double e = (a.hi - (s - bb)) + (b.hi - bb);
+  e += a.lo + b.lo;
+  double hi = s + e;
+  double lo = e - (hi - s);
+  return {hi, lo};
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+
+// One chirp sample: cos(2 pi frac(f0 t + fdot t^2 / 2)), t = n / fs.
+__device__ __forceinline__ double chirp_sample(double fs, double f0, double fdot, int n) {
+  double t = (double)n / fs;
+  double phi = f0 * t + 0.5 * fdot * (t * t);
+  phi = phi - floor(phi);
+  return cos(2.0 * 3.141592653589793 * phi);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Bank generation: one wave per template, float64 throughout, then quantisation.
+//
+// FP32 layout, per 32-template block b and 16-tap chunk c: 64 lanes x 8 floats, lane
+//   l = h*32 + m holding taps 16c + 2s + h (s = 0..7) of template 32b + m -- the A operand
+//   of eight successive v_mfma_f32_32x32x2_f32 steps.
+// BF16X3 layout, per (b, c): plane (hi, lo) x 64 lanes x 8 bf16, lane l = h*32 + m holding
+//   taps 16c + 8h + i (i = 0..7) of template 32b + m -- the A operand of one
+//   v_mfma_f32_32x32x16_bf16 step.
+// Padding templates (k >= K) and padding taps (n >= L) are zero.  The word after the bank
+// counts templates whose centred norm vanished (they cannot be normalised).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* dst,
+                                                  unsigned int* bad) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  if (k >= b.K_pad) return;
+  const bool real = k < b.K;
+  double f0 = 0.0, fdot = 0.0;
+  if (real) {
+    const int64_t il = k / g.n_fdot;
+    const int j = (int)(k % g.n_fdot);
+    const int64_t ig = g.f0_lo + il;
+    f0 = (g.n_f0 > 1 && ig == g.n_f0 - 1) ? g.f0_max : (double)ig * g.f0_step + g.f0_min;
+    fdot = (g.n_fdot > 1 && j == g.n_fdot - 1) ? g.fdot_max
+                                               : (double)j * g.fdot_step + g.fdot_min;
+  }
+  double mu = 0.0, nrm = 1.0;
+  if (real) {
+    double s1 = 0.0;
+    for (int n = lane; n < b.L; n += 64) s1 += chirp_sample(g.fs, f0, fdot, n);
+    mu = wave_sum_d(s1) / (double)b.L;
+    double s2 = 0.0;
+    for (int n = lane; n < b.L; n += 64) {
+      const double v = chirp_sample(g.fs, f0, fdot, n) - mu;
+      s2 += v * v;
+    }
+    s2 = wave_sum_d(s2);
+    nrm = sqrt(s2);
+    if (!(s2 > 1e-18 * (double)b.L)) {
+      if (lane == 0) atomicAdd(bad, 1u);
+      nrm = 1.0;
+    }
+  }
+  const int64_t blk = k >> 5;
+  const int m = (int)(k & 31);
+  for (int n = lane; n < b.L_pad; n += 64) {
+    const double h = (real && n < b.L) ? (chirp_sample(g.fs, f0, fdot, n) - mu) / nrm : 0.0;
+    const int c = n >> 4, r = n & 15;
+    if (b.precision == P_FP32) {
+      const int ln = (r & 1) * 32 + m, s = r >> 1;
+      float* out = (float*)dst;
+      out[(((int64_t)blk * b.n_chunks + c) * 64 + ln) * 8 + s] = (float)h;
+    } else {
+      const int ln = (r >> 3) * 32 + m, i = r & 7;
+      const double hi = round_bf16_d(h);
+      const double lo = round_bf16_d(h - hi);
+      uint16_t* out = (uint16_t*)dst;
+      const int64_t base = ((int64_t)blk * b.n_chunks + c) * 2;
+      out[((base + 0) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)hi) >> 16);
+      out[((base + 1) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)lo) >> 16);
+    }
+  }
+}
+
+hipError_t launch_bank_gen(const GridDev& g, const BankDev& b, void* dst, hipStream_t s) {
+  const size_t bank_bytes = (size_t)b.K_pad * (size_t)b.L_pad * 4;
+  unsigned int* bad = (unsigned int*)((char*)dst + bank_bytes);
+  hipError_t e = hipMemsetAsync(bad, 0, 256, s);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((b.K_pad + 3) / 4);
+  hipLaunchKernelGGL(k_bank_gen, dim3(grid), dim3(256), 0, s, g, b, dst, bad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Clearing: running maxima, spectrogram, spectrum sums, histogram, degenerate count.
+// grid = (X, n_segs); each series clears its own buffers with a grid-stride loop.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero(const SegDesc* __restrict__ segs, BankDev b,
+                                              SearchDev p) {
+  const SegDesc& sg = segs[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < sg.W; i += stride) sg.mkey[i] = 0ull;
+  if (sg.spec) {
+    const int64_t ns = sg.spec_rows * b.n_bins;
+    for (int64_t i = t0; i < ns; i += stride) sg.spec[i] = 0.0f;
+  }
+  for (int64_t i = t0; i < b.n_bins; i += stride) sg.spec_acc[i] = 0ull;
+  if (sg.hist)
+    for (int64_t i = t0; i < p.hist_bins; i += stride) sg.hist[i] = 0u;
+  if (sg.n_degenerate && t0 == 0) sg.n_degenerate[0] = 0;
+}
+
+hipError_t launch_zero(const SegDesc* segs_dev, int32_t n_segs, int64_t max_words,
+                       const BankDev& b, const SearchDev& p, hipStream_t s) {
+  int64_t blocks = (max_words + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
+                     segs_dev, b, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Prefix sums: one 1024-thread work-group per series scans x in tiles of 1024 samples,
+// carrying double-double sums of x and x^2 (non-finite samples count as 0 and are
+// counted separately).  pre[i] holds the sums over x[0..i).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_prefix(const SegDesc* __restrict__ segs) {
+  const SegDesc& sg = segs[blockIdx.x];
+  __shared__ dd w1[16], w2[16];
+  __shared__ int wc[16];
+  __shared__ dd c1s, c2s;
+  __shared__ int ccs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    c1s = {0.0, 0.0};
+    c2s = {0.0, 0.0};
+    ccs = 0;
+    sg.pre[0] = 0.0;
+    sg.pre[1] = 0.0;
+    sg.pre[2] = 0.0;
+    sg.pre[3] = 0.0;
+    sg.cnt[0] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < sg.n; base += 1024) {
+    const int64_t i = base + tid;
+    const float v = i < sg.n ? sg.x[i] : 0.0f;
+    const bool fin = isfinite(v);
+    const double a = fin ? (double)v : 0.0;
+    dd s1 = {a, 0.0}, s2 = {a * a, 0.0};  // a*a is exact for a float a
+    int c = (i < sg.n && !fin) ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const dd t1 = {__shfl_up(s1.hi, off, 64), __shfl_up(s1.lo, off, 64)};
+      const dd t2 = {__shfl_up(s2.hi, off, 64), __shfl_up(s2.lo, off, 64)};
+      const int tc = __shfl_up(c, off, 64);
+      if (lane >= off) {
+        s1 = dd_add(t1, s1);
+        s2 = dd_add(t2, s2);
+        c += tc;
+      }
+    }
+    if (lane == 63) {
+      w1[wave] = s1;
+      w2[wave] = s2;
+      wc[wave] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      dd r1 = c1s, r2 = c2s;
+      int rc = ccs;
+      for (int w = 0; w < 16; ++w) {
+        const dd t1 = w1[w], t2 = w2[w];
+        const int tc = wc[w];
+        w1[w] = r1;
+        w2[w] = r2;
+        wc[w] = rc;
+        r1 = dd_add(r1, t1);
+        r2 = dd_add(r2, t2);
+        rc += tc;
+      }
+      c1s = r1;
+      c2s = r2;
+      ccs = rc;
+    }
+    __syncthreads();
+    s1 = dd_add(w1[wave], s1);
+    s2 = dd_add(w2[wave], s2);
+    c += wc[wave];
+    if (i < sg.n) {
+      double* o = sg.pre + (i + 1) * 4;
+      o[0] = s1.hi;
+      o[1] = s1.lo;
+      o[2] = s2.hi;
+      o[3] = s2.lo;
+      sg.cnt[i + 1] = c;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_prefix(const SegDesc* segs_dev, int32_t n_segs, const BankDev&,
+                         const SearchDev&, hipStream_t s) {
+  hipLaunchKernelGGL(k_prefix, dim3((unsigned)n_segs), dim3(1024), 0, s, segs_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Window energies.  With D1 = sum x and D2 = sum x^2 over the window (double-double
+// differences of the prefix sums), the centred energy is E = (L*D2 - D1^2) / L, formed in
+// double-double so that windows with a large mean keep their small variance.  Raw: E = D2.
+// Degenerate (inv_norm = 0): a non-finite sample, R = D2 = 0, or E <= 1e-12 R.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_norms(const SegDesc* __restrict__ segs, int L,
+                                               int norm) {
+  const SegDesc& sg = segs[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tau < sg.W;
+       tau += stride) {
+    const double* a = sg.pre + tau * 4;
+    const double* z = sg.pre + (tau + L) * 4;
+    const dd d1 = dd_add({z[0], z[1]}, dd_neg({a[0], a[1]}));
+    const dd d2 = dd_add({z[2], z[3]}, dd_neg({a[2], a[3]}));
+    const int nc = sg.cnt[tau + L] - sg.cnt[tau];
+    const double R = d2.hi + d2.lo;
+    double E;
+    if (norm == 0) {
+      const double Ld = (double)L;
+      dd p1 = two_prod(Ld, d2.hi);
+      p1 = dd_add(p1, {Ld * d2.lo, 0.0});
+      dd p2 = two_prod(d1.hi, d1.hi);
+      p2 = dd_add(p2, {2.0 * d1.hi * d1.lo, 0.0});
+      const dd e = dd_add(p1, dd_neg(p2));
+      E = (e.hi + e.lo) / Ld;
+    } else {
+      E = R;
+    }
+    const bool degenerate = (nc > 0) || !(R > 0.0) || !(E > 1e-12 * R) || !isfinite(E);
+    sg.inv_norm[tau] = degenerate ? 0.0 : 1.0 / sqrt(E);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// The contraction with the fused reductions.
+//
+// Work item = (series, offset tile of N_WG offsets, bin range).  Items are numbered
+// range-major, so the work-groups resident at any time sweep the same templates and share
+// them through L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + N_WG + L_pad) (zero
+// past the end; non-finite samples as 0 -- their windows are degenerate and discarded),
+// then each wave sweeps the item's template tiles: for each tile, a full K-loop over the
+// taps into TM x TN accumulators of 32 x 32, then the epilogue.
+//
+// MFMA fragments (64 lanes, lane = h*32 + n):
+//   FP32  v_mfma_f32_32x32x2_f32: A lane holds h_k[kk + h] of template row n,
+//         B lane holds x[tau + kk + h] of offset column n.
+//   BF16  v_mfma_f32_32x32x16_bf16: A lane holds taps kk + 8h + i (i < 8), B lane holds
+//         x[tau + kk + 8h + i].  The strip is kept as four copies shifted by 0..3 samples,
+//         interleaved per 4-sample cell, so every lane's 8 consecutive samples are two
+//         8-byte-aligned LDS reads whatever tau is.  hi*hi + hi*lo + lo*hi are accumulated.
+//   Output lane holds column n, rows 8g + 4h + i4 (g, i4 < 4) in accumulator 4g + i4.
+// ---------------------------------------------------------------------------------------
+size_t main_lds_bytes(int precision, int L_pad) {
+  const size_t S = (size_t)N_WG + (size_t)L_pad + STRIP_SLACK;
+  return precision == P_FP32 ? S * 4 : S * 16;
+}
+
+struct ItemCtx {
+  int64_t tau0;     // first offset of the item
+  int64_t W;
+  int64_t k_lo, k_hi;  // local template range owned by the item (whole bins)
+};
+
+template <int PREC>
+struct AFrag;
+template <>
+struct AFrag<P_FP32> {
+  float4 v[TM][2];    // 8 taps per lane per block per chunk
+};
+template <>
+struct AFrag<P_BF16X3> {
+  uint4 v[TM][2];     // [block][plane hi/lo]
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t blk0, int c,
+                                       int nchunks, int lane) {
+  if constexpr (PREC == P_FP32) {
+    const float4* A = (const float4*)bank;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t idx = (((blk0 + t) * nchunks + c) * 64 + lane) * 2;
+      f.v[t][0] = A[idx];
+      f.v[t][1] = A[idx + 1];
+    }
+  } else {
+    const uint4* A = (const uint4*)bank;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t idx = (((blk0 + t) * nchunks + c) * 2) * 64 + lane;
+      f.v[t][0] = A[idx];
+      f.v[t][1] = A[idx + 64];
+    }
+  }
+}
+
+__device__ __forceinline__ float f4get(const float4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// B operand fragments of one 16-tap chunk, read from the LDS strip.
+template <int PREC>
+struct BFrag;
+template <>
+struct BFrag<P_FP32> {
+  float v[8][TN];     // [2-tap step][offset block]
+};
+template <>
+struct BFrag<P_BF16X3> {
+  uint4 v[TN][2];     // [offset block][plane hi/lo]
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_b(BFrag<PREC>& f, const char* lds, int off_w, int c,
+                                       int n, int h, int plane_bytes) {
+  if constexpr (PREC == P_FP32) {
+    const float* sx = (const float*)lds;
+    const int p0 = off_w + n + 16 * c + h;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) f.v[s][j] = sx[p0 + 32 * j + 2 * s];
+  } else {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int p = off_w + 32 * j + n + 16 * c + 8 * h;
+      const int addr = (p >> 2) * 32 + (p & 3) * 8;
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const uint2 u0 = *(const uint2*)(lds + pl * plane_bytes + addr);
+        const uint2 u1 = *(const uint2*)(lds + pl * plane_bytes + addr + 32);
+        f.v[j][pl] = make_uint4(u0.x, u0.y, u1.x, u1.y);
+      }
+    }
+  }
+}
+
+// The MFMAs of one 16-tap chunk.
+template <int PREC>
+__device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][TN], const AFrag<PREC>& a,
+                                          const BFrag<PREC>& bf) {
+  if constexpr (PREC == P_FP32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const float av = f4get(a.v[t][s >> 2], s & 3);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf.v[s][j], acc[t][j], 0, 0, 0);
+      }
+  } else {
+    // hi*hi, then hi*lo, then lo*hi: consecutive MFMAs write different accumulators.
+#pragma unroll
+    for (int term = 0; term < 3; ++term) {
+      const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const bf16x8 av = __builtin_bit_cast(bf16x8, a.v[t][pa]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const bf16x8 b = __builtin_bit_cast(bf16x8, bf.v[j][pb]);
+          acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b, acc[t][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// Spectrogram / spectrum flush of the current bin for this wave's TN x 32 offsets.
+__device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
+                                          const SearchDev& p, int bin, const float (&binmax)[TN],
+                                          const double (&inv)[TN], int64_t tau_w0, int n,
+                                          int h, int lane) {
+  unsigned long long fix = 0ull;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const float v = fmaxf(binmax[j], __shfl_xor(binmax[j], 32, 64));
+    const int64_t tau = tau_w0 + 32 * j + n;
+    if (h == 0 && tau < sg.W && inv[j] > 0.0) {
+      const float s = (float)((double)v * inv[j]);
+      if (sg.spec) {
+        unsigned int* dst =
+            (unsigned int*)sg.spec + (tau / p.t_block) * (int64_t)b.n_bins + bin;
+        atomicMax(dst, __float_as_uint(s));
+      }
+      fix += (unsigned long long)__double2ll_rn((double)s * SPEC_FIX_SCALE);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(fix & 0xFFFFFFFFull), o, 64);
+    const unsigned hi = __shfl_xor((unsigned)(fix >> 32), o, 64);
+    fix += ((unsigned long long)hi << 32) | lo;
+  }
+  if (lane == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restrict__ segs,
+                                                        BankDev b, SearchDev p) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = lane & 31, h = lane >> 5;
+
+  // ---- which item ----
+  const int64_t item = blockIdx.x;
+  const int r = (int)(item / p.total_tiles);
+  const int64_t tt = item % p.total_tiles;
+  int lo = 0, hi = p.n_segs - 1;
+  while (lo < hi) {  // last series with tile0 <= tt
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
+  }
+  const SegDesc& sg = segs[lo];
+  const int64_t tau0 = (tt - sg.tile0) * N_WG;
+  const int b_lo = (int)((int64_t)r * b.n_bins / p.n_ranges);
+  const int b_hi = (int)((int64_t)(r + 1) * b.n_bins / p.n_ranges);
+  const int64_t k_lo = (int64_t)b_lo * b.n_fdot;
+  const int64_t k_hi = (int64_t)b_hi * b.n_fdot;
+  const int64_t tile_lo = k_lo / TILE_K;
+  const int64_t tile_hi = (k_hi + TILE_K - 1) / TILE_K;
+
+  // ---- strip fill ----
+  const int S = N_WG + b.L_pad + STRIP_SLACK;  // multiple of 4
+  if constexpr (PREC == P_FP32) {
+    float* sx = (float*)lds;
+    for (int i = tid; i < S; i += WG_THREADS) {
+      const int64_t gi = tau0 + i;
+      float v = gi < sg.n ? sg.x[gi] : 0.0f;
+      sx[i] = isfinite(v) ? v : 0.0f;
+    }
+  } else {
+    // cell (q, c) of plane pl: samples x[tau0 + 4q + c + e], e = 0..3, as bf16 hi / lo.
+    const int plane_bytes = S * 8;
+    for (int t = tid; t < S; t += WG_THREADS) {
+      const int q = t >> 2, c = t & 3;
+      uint32_t hw[2] = {0u, 0u}, lw[2] = {0u, 0u};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gi = tau0 + 4 * q + c + e;
+        float v = gi < sg.n ? sg.x[gi] : 0.0f;
+        v = isfinite(v) ? v : 0.0f;
+        const uint32_t hb = bf16_bits(v);
+        const float hv = __uint_as_float(hb << 16);
+        const uint32_t lb = bf16_bits(v - hv);
+        hw[e >> 1] |= hb << (16 * (e & 1));
+        lw[e >> 1] |= lb << (16 * (e & 1));
+      }
+      *(uint2*)(lds + t * 8) = make_uint2(hw[0], hw[1]);
+      *(uint2*)(lds + plane_bytes + t * 8) = make_uint2(lw[0], lw[1]);
+    }
+  }
+  __syncthreads();
+
+  const int64_t tau_w0 = tau0 + (int64_t)wave * N_WAVE;
+  const int off_w = wave * N_WAVE;
+  const int plane_bytes = S * 8;
+
+  double inv[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int64_t tau = tau_w0 + 32 * j + n;
+    inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
+  }
+  float best[TN], binmax[TN];
+  int bestk[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    best[j] = -1.0f;
+    bestk[j] = -1;
+    binmax[j] = 0.0f;
+  }
+  int cur_bin = -1;
+  const int nfd = b.n_fdot;
+
+  for (int64_t kt = tile_lo; kt < tile_hi; ++kt) {
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[t][j] = (f32x16){};
+
+    const int64_t blk0 = kt * TM;
+    // Software pipeline over chunk pairs (n_chunks is even): while the MFMAs of chunk c
+    // run, the template fragments of chunk c+1 and the strip fragments of chunk c+1 are in
+    // flight.  Scheduling barriers keep the compiler from sinking the loads next to their
+    // uses.  The prefetches past the last chunk re-read a valid chunk and are unused.
+    const int nc = b.n_chunks;
+    AFrag<PREC> a0, a1;
+    BFrag<PREC> b0, b1;
+    __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
+    __builtin_amdgcn_sched_barrier(0);
+    load_a<PREC>(a0, b.data, blk0, 0, nc, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b<PREC>(b0, lds, off_w, 0, n, h, plane_bytes);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int c = 0; c < nc; c += 2) {
+      load_a<PREC>(a1, b.data, blk0, c + 1, nc, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b<PREC>(b1, lds, off_w, c + 1, n, h, plane_bytes);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk<PREC>(acc, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      const int c2 = c + 2 < nc ? c + 2 : nc - 1;
+      load_a<PREC>(a0, b.data, blk0, c2, nc, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b<PREC>(b0, lds, off_w, c2, n, h, plane_bytes);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk<PREC>(acc, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // ---- epilogue: lane rows are 32t + 8g + 4h + i4 of the tile ----
+    const int64_t kbase = kt * TILE_K;
+    const int r_lo = (int)((k_lo > kbase ? k_lo : kbase) - kbase);        // rows owned
+    const int r_hi = (int)((k_hi < kbase + TILE_K ? k_hi : kbase + TILE_K) - kbase);
+    const int bA = (int)((kbase + r_lo) / nfd), bB = (int)((kbase + r_hi - 1) / nfd);
+    if (r_lo == 0 && r_hi == TILE_K && bA == bB) {
+      // whole tile owned and inside one bin
+      if (bA != cur_bin) {
+        if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+        cur_bin = bA;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) binmax[j] = 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float a = fabsf(acc[t][j][v]);
+            const bool gt = a > best[j];
+            best[j] = gt ? a : best[j];
+            bestk[j] = gt ? (int)kbase + 32 * t + 8 * (v >> 2) + 4 * h + (v & 3) : bestk[j];
+            binmax[j] = fmaxf(binmax[j], a);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
+            const float a = fabsf(acc[t][j][v]);
+            const bool gt = row >= r_lo && row < r_hi && a > best[j];
+            best[j] = gt ? a : best[j];
+            bestk[j] = gt ? (int)kbase + row : bestk[j];
+          }
+      for (int bn = bA; bn <= bB; ++bn) {
+        if (bn != cur_bin) {
+          if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+          cur_bin = bn;
+#pragma unroll
+          for (int j = 0; j < TN; ++j) binmax[j] = 0.0f;
+        }
+        const int64_t e_lo = (int64_t)bn * nfd - kbase, e_hi = (int64_t)(bn + 1) * nfd - kbase;
+        const int q_lo = (int)(e_lo > r_lo ? e_lo : r_lo);
+        const int q_hi = (int)(e_hi < r_hi ? e_hi : r_hi);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int t = 0; t < TM; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
+              const float a = fabsf(acc[t][j][v]);
+              binmax[j] = (row >= q_lo && row < q_hi) ? fmaxf(binmax[j], a) : binmax[j];
+            }
+      }
+    }
+  }
+  if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+
+  // ---- per-offset maxima: combine the two row halves, then one atomic per offset ----
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const float ov = __shfl_xor(best[j], 32, 64);
+    const int ok = __shfl_xor(bestk[j], 32, 64);
+    if (ov > best[j] || (ov == best[j] && ok >= 0 && (bestk[j] < 0 || ok < bestk[j]))) {
+      best[j] = ov;
+      bestk[j] = ok;
+    }
+    const int64_t tau = tau_w0 + 32 * j + n;
+    if (h == 0 && tau < sg.W && bestk[j] >= 0) {
+      const unsigned int kg = (unsigned int)(b.k_offset + bestk[j]);
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(best[j]) << 32) | (0xFFFFFFFFull - kg);
+      atomicMax(sg.mkey + tau, key);
+    }
+  }
+}
+
+hipError_t launch_main(const SegDesc* segs_dev, const BankDev& b, const SearchDev& p,
+                       hipStream_t s) {
+  const size_t lds = main_lds_bytes(b.precision, b.L_pad);
+  const int64_t items = p.total_tiles * p.n_ranges;
+  if (b.precision == P_FP32) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_main<P_FP32>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_main<P_FP32>, dim3((unsigned)items), dim3(WG_THREADS), lds, s,
+                       segs_dev, b, p);
+  } else if (b.precision == P_BF16X3) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_main<P_BF16X3>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_main<P_BF16X3>, dim3((unsigned)items), dim3(WG_THREADS), lds, s,
+                       segs_dev, b, p);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Finalise: m = f32(|d|max * inv_norm) in float64, argmax from the packed key, histogram of
+// m over non-degenerate windows (LDS-privatised), degenerate count, spectrum = fixed-point
+// sum / (2^40 W).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(const SegDesc* __restrict__ segs, BankDev b,
+                                                  SearchDev p) {
+  const SegDesc& sg = segs[blockIdx.y];
+  __shared__ unsigned int hl[MAX_HIST_BINS];
+  __shared__ unsigned int ndeg;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < p.hist_bins; i += 256) hl[i] = 0u;
+  if (tid == 0) ndeg = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned int my_deg = 0u;
+  const double span = p.hist_hi - p.hist_lo;
+  for (int64_t tau = (int64_t)blockIdx.x * blockDim.x + tid; tau < sg.W; tau += stride) {
+    const double inv = sg.inv_norm[tau];
+    if (inv > 0.0) {
+      const unsigned long long key = sg.mkey[tau];
+      const float d = __uint_as_float((unsigned int)(key >> 32));
+      const float m = (float)((double)d * inv);
+      const int a = (int)(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
+      if (sg.max_abs) sg.max_abs[tau] = m;
+      if (sg.argmax) sg.argmax[tau] = a;
+      double q = floor(((double)m - p.hist_lo) / span * (double)p.hist_bins);
+      q = q > 0.0 ? q : 0.0;  // also maps NaN to bin 0
+      q = q > (double)(p.hist_bins - 1) ? (double)(p.hist_bins - 1) : q;
+      atomicAdd(&hl[(int)q], 1u);
+    } else {
+      if (sg.max_abs) sg.max_abs[tau] = 0.0f;
+      if (sg.argmax) sg.argmax[tau] = -1;
+      ++my_deg;
+    }
+  }
+  if (my_deg) atomicAdd(&ndeg, my_deg);
+  __syncthreads();
+  if (sg.hist)
+    for (int i = tid; i < p.hist_bins; i += 256)
+      if (hl[i]) atomicAdd(sg.hist + i, hl[i]);
+  if (tid == 0 && sg.n_degenerate && ndeg)
+    atomicAdd((unsigned long long*)sg.n_degenerate, (unsigned long long)ndeg);
+  if (blockIdx.x == 0 && sg.spectrum)
+    for (int i = tid; i < b.n_bins; i += 256)
+      sg.spectrum[i] = (double)sg.spec_acc[i] / SPEC_FIX_SCALE / (double)sg.W;
+}
+
+hipError_t launch_finalize(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W,
+                           const BankDev& b, const SearchDev& p, hipStream_t s) {
+  int64_t blocks = (max_W + 1023) / 1024;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
+                     segs_dev, b, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W, int L,
+                        int norm, hipStream_t s) {
+  int64_t blocks = (max_W + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_norms, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
+                     segs_dev, L, norm);
+  return hipGetLastError();
+}
+
+}  // namespace bfly

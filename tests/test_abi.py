@@ -1,0 +1,57 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point include/bfly.h
+declares, and its host-side validation answers without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfly.h")
+LIB = os.path.join(ROOT, "paper_1802_01685_amd", "libbfly.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:bf_status|const char\*)\s+(bf_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libbfly.so is not built (run `python -m paper_1802_01685_amd.build`)")
+    from paper_1802_01685_amd import bfly
+    return bfly
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy",
+              "bf_workspace_bytes", "bf_search_segment", "bf_search_batch", "bf_plan",
+              "bf_set_timing", "bf_kernel_times", "bf_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = ctypes.CDLL(LIB)
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert sorted(lib.EXPORTED) == declared_symbols()
+
+
+def test_bank_bytes_and_validation_on_host(lib):
+    from synth import bank_params
+    d = lib.make_desc(bank_params(2), "bf16x3")
+    # K_pad * L_pad * 4 bytes + a 256-byte status word
+    assert lib.bank_bytes(d) == 65536 * 4096 * 4 + 256
+    d3 = lib.make_desc(bank_params(3), "fp32")
+    assert lib.bank_bytes(d3) == 720000 * 2016 * 4 + 256   # L_pad = 2016 (multiple of 32)
+    for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
+                {"f0_max": 1.0}, {"precision": 7}):
+        q = lib.make_desc(bank_params(2), "fp32")
+        for k, v in bad.items():
+            setattr(q, k, v)
+        with pytest.raises(lib.BflyError) as e:
+            lib.bank_bytes(q)
+        assert e.value.status == lib.BF_EINVAL
+        assert lib.last_error() != ""

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Tolerances (max relative error of the butterfly output m and of the spectrogram S over
+non-degenerate offsets): FP32 1e-5, BF16 hi/lo split 1e-4.  Argmax: the template the GPU
+reports must reach the FP64 maximum within 2*tol (so it must be the oracle's template
+wherever the FP64 top-2 margin exceeds 2*tol*m).  Histograms: exact against the floor-rule
+binning of the GPU's own maxima, and equal to the FP64 histogram except for maxima within
+tol of a bin edge.  Integer and index outputs of batched and single searches must be
+identical bit for bit.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bfly_oracle as O  # noqa: E402
+from synth import (BankParams, bank_params, cfg1_series, cfg2_series, cfg3_series,  # noqa: E402
+                   chirp_samples, time_randomised, white_noise)
+from tests.parity_util import TOL, check_against_oracle, check_hist, to_np  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp32", "bf16x3"]
+
+
+@pytest.fixture(scope="module")
+def bf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_01685_amd import bfly
+    bfly.lib()
+    return bfly
+
+
+def _run(bf, p, x32, prec, t_block=1, norm="centred", hist_bins=256, lo=0.0, hi=1.0):
+    bank = bf.bank_create(p, prec)
+    prm = bf.make_params(norm=norm, t_block=t_block, hist_bins=hist_bins, hist_lo=lo, hist_hi=hi)
+    x = torch.from_numpy(np.ascontiguousarray(x32, dtype=np.float32)).cuda()
+    out = bf.search_segment(bank, x, prm)
+    torch.cuda.synchronize()
+    return to_np(out), bank
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cfg1_full(bf, prec):
+    """4 s at 512 Hz, bank 16x16, L = 512: every one of the 1537 offsets."""
+    p = bank_params(1)
+    x32 = cfg1_series().astype(np.float32)
+    x64 = x32.astype(np.float64)
+    g, _ = _run(bf, p, x32, prec)
+    orc = O.search(x64, p)
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"cfg1/{prec}")
+    check_hist(g, orc["m"], orc["degen"], TOL[prec], 256, 0.0, 1.0, f"cfg1/{prec}")
+    assert np.allclose(g["spectrum"], orc["spectrum"], rtol=TOL[prec], atol=0)
+    print(f"cfg1 {prec}: {st}")
+
+
+def _edge_series(n, seed, L):
+    x = white_noise(n, seed)
+    x[n // 3: n // 3 + L + 5] = 1.25            # constant run -> degenerate windows
+    x[n // 2: n // 2 + L + 2] = 0.0             # zero run -> degenerate windows
+    x[(2 * n) // 3] = np.nan                     # NaN -> L windows degenerate
+    x[(2 * n) // 3 + 3 * L] = np.inf
+    return x.astype(np.float32)
+
+
+SMALL = {
+    # name: (bank, n, norm, t_block, edge cases)
+    "ragged": (BankParams(fs=128.0, L=48, n_f0=5, n_fdot=7, f0_min=3.0, f0_max=40.0,
+                          fdot_min=-30.0, fdot_max=25.0), 1500, "centred", 1, True),
+    "L_odd": (BankParams(fs=100.0, L=37, n_f0=3, n_fdot=40, f0_min=4.0, f0_max=30.0,
+                         fdot_min=-50.0, fdot_max=50.0), 700, "centred", 1, False),
+    "W_is_1": (BankParams(fs=64.0, L=64, n_f0=4, n_fdot=16, f0_min=2.0, f0_max=20.0,
+                          fdot_min=-10.0, fdot_max=10.0), 64, "centred", 1, False),
+    "sharded_raw": (BankParams(fs=256.0, L=100, n_f0=7, n_fdot=24, f0_min=5.0, f0_max=80.0,
+                               fdot_min=-60.0, fdot_max=60.0, shard_index=1, shard_count=3),
+                    2000, "raw", 1, True),
+    "t_block": (BankParams(fs=200.0, L=50, n_f0=6, n_fdot=9, f0_min=3.0, f0_max=60.0,
+                           fdot_min=-40.0, fdot_max=40.0), 1600, "centred", 7, True),
+    "wide_bins": (BankParams(fs=128.0, L=64, n_f0=3, n_fdot=150, f0_min=5.0, f0_max=50.0,
+                             fdot_min=-80.0, fdot_max=80.0), 1200, "centred", 1, False),
+}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_shapes(bf, name, prec):
+    p, n, norm, t_block, edges = SMALL[name]
+    x32 = _edge_series(n, 7, p.L) if edges else white_noise(n, 8).astype(np.float32)
+    x64 = x32.astype(np.float64)
+    g, bank = _run(bf, p, x32, prec, t_block=t_block, norm=norm, hist_bins=64)
+    orc = O.search(x64, p, norm=norm, hist_bins=64)
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"{name}/{prec}", t_block=t_block)
+    check_hist(g, orc["m"], orc["degen"], TOL[prec], 64, 0.0, 1.0, f"{name}/{prec}")
+    if edges:
+        assert st["n_degenerate"] > 0
+    if t_block > 1:
+        want = O.decimate(orc["S"], t_block)
+        got = g["spec"].astype(np.float64)
+        pos = want > 0
+        assert np.all(np.abs(got[pos] - want[pos]) <= TOL[prec] * want[pos])
+        assert np.all(got[~pos] == 0.0)
+    W = n - p.L + 1
+    # spectrum: time mean of the undecimated spectrogram
+    assert np.allclose(g["spectrum"], orc["spectrum"], rtol=TOL[prec], atol=1e-12)
+    assert bank.k_offset == O.grid(p).k_global[0]
+    assert g["max_abs"].shape == (W,)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_equals_single_bitwise(bf, prec):
+    """Uneven series (and a time-randomised control) in one batch give exactly the outputs
+    of searching each alone."""
+    p = BankParams(fs=256.0, L=96, n_f0=6, n_fdot=20, f0_min=5.0, f0_max=90.0,
+                   fdot_min=-70.0, fdot_max=70.0)
+    xs = [_edge_series(3000, 1, p.L), white_noise(96, 2).astype(np.float32),
+          white_noise(1777, 3).astype(np.float32)]
+    xs.append(time_randomised(xs[2], 103))
+    bank = bf.bank_create(p, prec)
+    prm = bf.make_params(t_block=3, hist_bins=32)
+    xt = [torch.from_numpy(x).cuda() for x in xs]
+    batch = [to_np(o) for o in bf.search_batch(bank, xt, prm)]
+    single = [to_np(bf.search_segment(bank, x, prm)) for x in xt]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(batch, single)):
+        for k in a:
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), (i, k)
+
+
+def test_determinism(bf):
+    p = bank_params(1)
+    x32 = cfg1_series().astype(np.float32)
+    a, _ = _run(bf, p, x32, "bf16x3")
+    b, _ = _run(bf, p, x32, "bf16x3")
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_on_grid_recovery(bf, prec):
+    """A bank template's chirp (amplitude 0.5) injected at sample 666 into unit noise is
+    found at exactly that offset and template."""
+    p = bank_params(1)
+    gr = O.grid(p)
+    k = 3 * 16 + 11
+    for seed in (1, 2):
+        x = white_noise(2048, seed)
+        sig, _ = chirp_samples(2048, p.fs, 666 / p.fs, gr.f0[k], gr.fdot[k])
+        x32 = (x + 0.5 * sig).astype(np.float32)
+        g, _ = _run(bf, p, x32, prec)
+        i = int(np.argmax(g["max_abs"]))
+        assert i == 666 and g["argmax"][i] == k, (seed, i, g["argmax"][i])
+
+
+def _sample_offsets(W, centre, n_block, n_rand, seed):
+    rng = np.random.default_rng(seed)
+    blk = np.arange(max(0, centre - n_block // 2), min(W, centre + n_block // 2))
+    rnd = rng.choice(W, n_rand, replace=False)
+    return np.unique(np.concatenate([blk, rnd, [0, W - 1]]))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cfg2_full_size_sampled(bf, prec):
+    """32 s at 4096 Hz against 65,536 templates of L = 4096, at full size; the oracle checks
+    a contiguous block around the injection plus random offsets and the two ends."""
+    p = bank_params(2)
+    x32 = cfg2_series()
+    x64 = x32.astype(np.float64)
+    g, _ = _run(bf, p, x32, prec)
+    W = x32.shape[0] - p.L + 1
+    offs = _sample_offsets(W, 49152, 48, 80, seed=22)
+    orc = O.search(x64, p, offsets=offs)
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"cfg2/{prec}")
+    # properties at every offset
+    assert np.array_equal(g["hist"], O.histogram(g["max_abs"].astype(np.float64),
+                                                 g["argmax"] < 0, 256, 0.0, 1.0))
+    spec = g["spec"].astype(np.float64)
+    assert np.array_equal(spec.max(axis=1), g["max_abs"].astype(np.float64))
+    assert np.allclose(g["spectrum"] * W, spec.sum(axis=0), rtol=1e-9, atol=0)
+    assert np.all(g["max_abs"] <= 1.0 + 1e-5)
+    print(f"cfg2 {prec}: {st}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cfg3_share_with_control_sampled(bf, prec):
+    """One GPU's 720,000-template share (L = 2000) against the 64 s light curve and its
+    time-randomised control in one batch; oracle on sampled offsets of both."""
+    p = bank_params(3)
+    x = cfg3_series()
+    xc = cfg3_series(control=True)
+    bank = bf.bank_create(p, prec)
+    prm = bf.make_params()
+    outs = bf.search_batch(bank, [torch.from_numpy(x).cuda(), torch.from_numpy(xc).cuda()], prm)
+    torch.cuda.synchronize()
+    g = [to_np(o) for o in outs]
+    W = x.shape[0] - p.L + 1
+    offs = [_sample_offsets(W, W // 2, 16, 24, seed=33), _sample_offsets(W, W // 3, 16, 24, 34)]
+    orcs = O.search_many([x.astype(np.float64), xc.astype(np.float64)], p, offs)
+    for gi, oi, xi, lab in zip(g, orcs, (x, xc), ("data", "control")):
+        st = check_against_oracle(xi.astype(np.float64), p, gi, oi, TOL[prec], f"cfg3/{lab}/{prec}")
+        assert np.array_equal(gi["hist"], O.histogram(gi["max_abs"].astype(np.float64),
+                                                      gi["argmax"] < 0, 256, 0.0, 1.0))
+        print(f"cfg3 {lab} {prec}: {st}")
+    # the control keeps the value histogram of the data
+    assert np.array_equal(np.sort(x), np.sort(xc))
