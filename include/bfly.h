@@ -157,6 +157,69 @@ bf_status bf_search_batch(const bf_bank* bank, const bf_segment* segs, int32_t n
                           const bf_search_params* params, void* workspace,
                           size_t workspace_bytes, bf_stream stream);
 
+/* ---- Serving: continuous batching with a device-resident bank --------------------------
+ * A server owns a worker thread, `ticks_in_flight` HIP streams and one device allocation of
+ * hbm_budget_bytes from which each admitted request takes its buffers (samples, workspace,
+ * outputs; bf_server_request_bytes).  bf_submit copies the samples to pinned host memory and
+ * returns at once.  Requests are admitted in arrival order while fewer than max_slots hold
+ * device memory and their buffers fit the budget; admitted requests are searched in ticks:
+ * one batched search per tick over every admitted, not yet launched request, replaying a
+ * HIP graph captured at creation (table upload + the five kernels) on a free stream.
+ * Requests arriving while ticks run join the next tick, which overlaps the running ones on
+ * the device.  A request's results are identical, bit for bit, alone or in any mix.
+ * Thread-safe: any thread may submit, poll, fetch and cancel. */
+typedef struct bf_server bf_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device bytes for request buffers, >= 1 MiB */
+  int32_t max_slots;        /* requests holding device memory at once, 1..1024 */
+  int32_t ticks_in_flight;  /* concurrent ticks (streams), 1..4 */
+  int32_t reserved;         /* must be 0 */
+  int32_t reserved2;        /* must be 0 */
+  bf_search_params params;  /* applied to every request */
+} bf_server_desc;
+
+typedef enum { BF_QUEUED = 0, BF_RUNNING = 1, BF_DONE = 2, BF_FAILED = 3, BF_CANCELLED = 4 }
+    bf_request_state;
+
+/* Creates a server for a bank (which must outlive it) on the current device; allocates the
+ * budget and captures one graph per stream.  BF_ENOMEM if the budget cannot be allocated. */
+bf_status bf_server_create(const bf_bank* bank, const bf_server_desc* desc, bf_server** out);
+
+/* Device bytes a request of n samples takes from the budget. */
+bf_status bf_server_request_bytes(const bf_server* server, int64_t n, size_t* bytes);
+
+/* Queues a search of x_host (host, n float32 samples, copied before returning).  *ticket
+ * identifies the request.  BF_EBUDGET if the request cannot fit the budget even alone,
+ * BF_EINVAL if n < L. */
+bf_status bf_submit(bf_server* server, const float* x_host, int64_t n, uint64_t* ticket);
+
+/* State (bf_request_state) and times in seconds since the server's creation: submitted,
+ * launched (0 while queued), finished (0 until done).  Any pointer may be NULL.
+ * BF_ENOTFOUND for an unknown or already fetched ticket. */
+bf_status bf_poll(bf_server* server, uint64_t ticket, int32_t* state, double* t_submit,
+                  double* t_start, double* t_done);
+
+/* Copies a finished request's outputs (host buffers sized as for bf_search_segment; any may
+ * be NULL) and forgets the ticket.  BF_EAGAIN while queued or running (the ticket stays);
+ * BF_ECANCELED for a cancelled request and BF_EHIP for a failed one (the ticket is
+ * forgotten); BF_ENOTFOUND for an unknown ticket. */
+bf_status bf_fetch(bf_server* server, uint64_t ticket, float* max_abs, int32_t* argmax,
+                   float* spec, double* spectrum, uint32_t* hist, int64_t* n_degenerate);
+
+/* Cancels a request: a queued one is dropped, an admitted or running one completes and its
+ * result is discarded (its state becomes BF_CANCELLED).  BF_ENOTFOUND if unknown. */
+bf_status bf_cancel(bf_server* server, uint64_t ticket);
+
+/* Counters: requests done, ticks launched, correlations done, requests queued, requests
+ * holding device memory.  Any pointer may be NULL. */
+bf_status bf_server_stats(bf_server* server, int64_t* done, int64_t* ticks,
+                          double* correlations, int32_t* queued, int32_t* on_device);
+
+/* Drops queued requests, waits for running ticks, frees everything.  Unfetched results are
+ * lost. */
+bf_status bf_server_destroy(bf_server* server);
+
 /* Work decomposition the searches would use for series of lengths n[0..n_segs-1] (host):
  * the bank sweep is split into *n_ranges contiguous ranges of whole f0 bins, and each
  * (series, block of offsets, range) is one work item of the contraction kernel. */
@@ -165,10 +228,12 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
 
 /* Profiling aid.  With timing enabled, every search records HIP events on its stream
  * around each of its five kernels (clear, prefix sums, window norms, contraction,
- * finalise).  bf_kernel_times waits for the calling thread's last search and writes the
- * five durations in milliseconds to ms[0..4] (host); BF_EAGAIN if no timed search ran. */
+ * finalise); the calling thread keeps the records of up to 256 searches.  bf_kernel_times
+ * waits for those searches, writes the summed durations in milliseconds per kernel to
+ * ms[0..4] (host) and their number to *n_searches (may be NULL), and forgets them.
+ * BF_EAGAIN if no timed search ran on this thread since the last collection. */
 bf_status bf_set_timing(int32_t enable);
-bf_status bf_kernel_times(double* ms);
+bf_status bf_kernel_times(double* ms, int32_t* n_searches);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* bf_last_error(void);

@@ -25,7 +25,10 @@ STATUS_NAMES = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ENOMEM", -3: "BF_EBUDGET",
                 -4: "BF_EAGAIN", -5: "BF_ENOTFOUND", -6: "BF_EHIP", -7: "BF_ECANCELED"}
 EXPORTED = ["bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy",
             "bf_workspace_bytes", "bf_search_segment", "bf_search_batch", "bf_plan",
-            "bf_set_timing", "bf_kernel_times", "bf_last_error"]
+            "bf_set_timing", "bf_kernel_times", "bf_last_error",
+            "bf_server_create", "bf_server_request_bytes", "bf_submit", "bf_poll", "bf_fetch",
+            "bf_cancel", "bf_server_stats", "bf_server_destroy"]
+STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
 class BflyError(RuntimeError):
@@ -58,6 +61,12 @@ class Segment(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", Result)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("ticks_in_flight", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32), ("params", SearchParams)]
+
+
 _lib = None
 
 
@@ -85,7 +94,18 @@ def lib() -> ctypes.CDLL:
                             sz, vp],
         "bf_plan": [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "bf_set_timing": [i32],
-        "bf_kernel_times": [ctypes.POINTER(ctypes.c_double)],
+        "bf_kernel_times": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+        "bf_server_create": [vp, ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)],
+        "bf_server_request_bytes": [vp, i64, ctypes.POINTER(sz)],
+        "bf_submit": [vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)],
+        "bf_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+        "bf_fetch": [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, vp],
+        "bf_cancel": [vp, ctypes.c_uint64],
+        "bf_server_stats": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
+                            ctypes.POINTER(i32)],
+        "bf_server_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -262,8 +282,95 @@ def set_timing(enable: bool) -> None:
     _check(lib().bf_set_timing(1 if enable else 0))
 
 
-def kernel_times() -> dict:
-    """Milliseconds of the calling thread's last timed search, per kernel."""
+def kernel_times() -> tuple[dict, int]:
+    """Summed milliseconds per kernel over the calling thread's timed searches since the
+    last call, and how many searches that was."""
     ms = (ctypes.c_double * 5)()
-    _check(lib().bf_kernel_times(ms))
-    return dict(zip(("zero", "prefix", "norms", "main", "finalize"), list(ms)))
+    cnt = ctypes.c_int32()
+    _check(lib().bf_kernel_times(ms, ctypes.byref(cnt)))
+    return dict(zip(("zero", "prefix", "norms", "main", "finalize"), list(ms))), cnt.value
+
+
+# ---- serving ------------------------------------------------------------------------------
+class Server:
+    """A serving handle; keeps its bank alive."""
+
+    def __init__(self, handle: int, bank: Bank, params: SearchParams):
+        self.handle = handle
+        self.bank = bank
+        self.params = params
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bf_server_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+
+def server_create(bank: Bank, hbm_budget_bytes: int, max_slots: int = 16,
+                  ticks_in_flight: int = 2, params: SearchParams | None = None) -> Server:
+    params = params or make_params()
+    d = ServerDesc(hbm_budget_bytes=int(hbm_budget_bytes), max_slots=max_slots,
+                   ticks_in_flight=ticks_in_flight, reserved=0, reserved2=0, params=params)
+    h = ctypes.c_void_p()
+    _check(lib().bf_server_create(ctypes.c_void_p(bank.handle), ctypes.byref(d), ctypes.byref(h)))
+    return Server(h.value, bank, params)
+
+
+def server_request_bytes(server: Server, n: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().bf_server_request_bytes(ctypes.c_void_p(server.handle), int(n), ctypes.byref(out)))
+    return out.value
+
+
+def submit(server: Server, x) -> int:
+    """Queues a float32 host series (numpy array); returns its ticket."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = ctypes.c_uint64()
+    _check(lib().bf_submit(ctypes.c_void_p(server.handle), x.ctypes.data, x.shape[0],
+                           ctypes.byref(t)))
+    return t.value
+
+
+def poll(server: Server, ticket: int) -> tuple[str, float, float, float]:
+    st = ctypes.c_int32()
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().bf_poll(ctypes.c_void_p(server.handle), ticket, ctypes.byref(st),
+                         ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return STATES[st.value], a.value, b.value, c.value
+
+
+def fetch(server: Server, ticket: int, n: int) -> dict:
+    """Outputs of a finished request of n samples as numpy arrays."""
+    import numpy as np
+    W = n - server.bank.desc.L + 1
+    rows = -(-W // server.params.t_block)
+    out = {"max_abs": np.empty(W, np.float32), "argmax": np.empty(W, np.int32),
+           "spec": np.empty((rows, server.bank.n_bins), np.float32),
+           "spectrum": np.empty(server.bank.n_bins, np.float64),
+           "hist": np.empty(server.params.hist_bins, np.uint32),
+           "n_degenerate": np.empty(1, np.int64)}
+    _check(lib().bf_fetch(ctypes.c_void_p(server.handle), ticket, out["max_abs"].ctypes.data,
+                          out["argmax"].ctypes.data, out["spec"].ctypes.data,
+                          out["spectrum"].ctypes.data, out["hist"].ctypes.data,
+                          out["n_degenerate"].ctypes.data))
+    return out
+
+
+def cancel(server: Server, ticket: int) -> None:
+    _check(lib().bf_cancel(ctypes.c_void_p(server.handle), ticket))
+
+
+def server_stats(server: Server) -> dict:
+    d, t, q, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    c = ctypes.c_double()
+    _check(lib().bf_server_stats(ctypes.c_void_p(server.handle), ctypes.byref(d), ctypes.byref(t),
+                                 ctypes.byref(c), ctypes.byref(q), ctypes.byref(o)))
+    return {"done": d.value, "ticks": t.value, "correlations": c.value, "queued": q.value,
+            "on_device": o.value}
+
+
+def server_destroy(server: Server) -> None:
+    if server.handle:
+        _check(lib().bf_server_destroy(ctypes.c_void_p(server.handle)))
+        server.handle = None

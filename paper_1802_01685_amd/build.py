@@ -2,7 +2,8 @@
 
     python -m paper_1802_01685_amd.build
 
-Compiles csrc/bfly_kernels.hip and csrc/bfly_api.cpp with hipcc and links them into
+Compiles csrc/bfly_kernels.hip, csrc/bfly_api.cpp and csrc/bfly_server.cpp with hipcc and
+links them into
 paper_1802_01685_amd/libbfly.so next to this file.  Always recompiles.
 """
 
@@ -21,6 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfly.so")
 
 ARCH = "gfx950"
+SOURCES = ["bfly_kernels.hip", "bfly_api.cpp", "bfly_server.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     "-ffp-contract=off",
@@ -49,12 +51,13 @@ def _run(cmd: list[str]) -> None:
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     with tempfile.TemporaryDirectory(prefix="bfly_build_") as tmp:
-        k_obj = os.path.join(tmp, "bfly_kernels.o")
-        a_obj = os.path.join(tmp, "bfly_api.o")
-        _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "bfly_kernels.hip"), "-o", k_obj])
-        _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "bfly_api.cpp"), "-o", a_obj])
+        objs = []
+        for src in SOURCES:
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
+            _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
+            objs.append(obj)
         tmp_lib = os.path.join(tmp, "libbfly.so")
-        _run([hipcc, *DEVICE, "-shared", "-fPIC", k_obj, a_obj, "-o", tmp_lib])
+        _run([hipcc, *DEVICE, "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp_lib])
         shutil.copyfile(tmp_lib, LIB + ".tmp")
         os.replace(LIB + ".tmp", LIB)
     if verbose:

@@ -6,6 +6,7 @@
 // thread-local message.
 #include "bfly.h"
 #include "bfly_internal.h"
+#include "bfly_runtime.h"
 
 #include <hip/hip_runtime.h>
 
@@ -13,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -21,18 +23,13 @@
 
 using namespace bfly;
 
-struct bf_bank {
-  bf_bank_desc desc;
-  GridDev grid;
-  BankDev dev;
-  int device;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-bf_status fail(bf_status code, const char* fmt, ...) {
+namespace bfly {
+
+bf_status set_error(bf_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -42,9 +39,16 @@ bf_status fail(bf_status code, const char* fmt, ...) {
   return code;
 }
 
-bf_status hip_fail(hipError_t e, const char* what) {
-  return fail(BF_EHIP, "%s: %s", what, hipGetErrorString(e));
+bf_status hip_error(hipError_t e, const char* what) {
+  return set_error(BF_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace bfly
+
+namespace {
+
+#define fail ::bfly::set_error
+#define hip_fail ::bfly::hip_error
 
 #define HIP_TRY(call, what)                     \
   do {                                          \
@@ -62,7 +66,7 @@ bf_status check_desc(const bf_bank_desc* d) {
   if (d->shard_count < 1 || d->shard_index < 0 || d->shard_index >= d->shard_count ||
       d->shard_count > d->n_f0)
     return fail(BF_EINVAL, "need 0 <= shard_index < shard_count <= n_f0");
-  if (d->precision != BF_FP32 && d->precision != BF_BF16X3)
+  if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8)
     return fail(BF_EINVAL, "precision %d is not available", d->precision);
   const double v[4] = {d->f0_min, d->f0_max, d->fdot_min, d->fdot_max};
   for (double x : v)
@@ -96,12 +100,11 @@ void fill_geometry(const bf_bank_desc* d, GridDev* g, BankDev* b) {
   b->K_pad = round_up(b->K, TILE_K);
   b->k_offset = f0_lo * d->n_fdot;
   b->L = d->L;
-  b->L_pad = (int32_t)round_up(d->L, 2 * KCH);
-  b->n_chunks = b->L_pad / KCH;
+  b->texp = nullptr;
+  b->L_pad = (int32_t)round_up(d->L, 2 * chunk_taps(d->precision));
+  b->n_chunks = b->L_pad / chunk_taps(d->precision);
   b->precision = d->precision;
 }
-
-size_t bank_data_bytes(const BankDev& b) { return (size_t)b.K_pad * (size_t)b.L_pad * 4; }
 
 // The grid value numpy.linspace produces: i*step + start, the last point exactly stop.
 double grid_value(double lo, double hi, double step, int n, int64_t i) {
@@ -180,42 +183,130 @@ void release_staging(Staging* s, bool recorded) {
   s->busy = false;
 }
 
-// ---- optional per-kernel timing ---------------------------------------------------------
-bool g_timing = false;
-struct TimingEvents {
-  hipEvent_t ev[6] = {};
-  int device = -1;
-  bool valid = false;
-};
-thread_local TimingEvents t_timing;
+int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
-// ---- workspace layout ------------------------------------------------------------------
-struct SegLayout {
-  size_t pre, cnt, inv_norm, mkey, spec_acc;
-};
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// Computes the byte offsets of every series' buffers; returns the total size.
-size_t layout(const BankDev& b, const int64_t* n, int32_t n_segs, std::vector<SegLayout>* out) {
-  size_t off = align256((size_t)n_segs * sizeof(SegDesc));
-  if (out) out->resize((size_t)n_segs);
-  for (int32_t i = 0; i < n_segs; ++i) {
-    const int64_t W = n[i] - b.L + 1;
-    SegLayout s;
-    s.pre = off;
-    off = align256(off + (size_t)(n[i] + 1) * 4 * sizeof(double));
-    s.cnt = off;
-    off = align256(off + (size_t)(n[i] + 1) * sizeof(int32_t));
-    s.inv_norm = off;
-    off = align256(off + (size_t)W * sizeof(double));
-    s.mkey = off;
-    off = align256(off + (size_t)W * sizeof(unsigned long long));
-    s.spec_acc = off;
-    off = align256(off + (size_t)b.n_bins * sizeof(unsigned long long));
-    if (out) (*out)[(size_t)i] = s;
+// Offset blocks of 32 per wave of the contraction kernel.  BF_TN=4|8 overrides the default
+// (a tuning knob for experiments).
+int32_t choose_tn(int precision) {
+  static int forced = -1;
+  if (forced < 0) {
+    const char* e = getenv("BF_TN");
+    forced = (e && (atoi(e) == 4 || atoi(e) == 8)) ? atoi(e) : 0;
   }
+  if (forced) return forced;
+  return precision == BF_FP32 ? 4 : 4;
+}
+
+// Per-thread pool of timing records, collected by bf_kernel_times.  The events live until
+// the process ends: destroying them from a thread-exit destructor could run after the HIP
+// runtime has shut down.
+bool g_timing = false;
+constexpr int MAX_TIMED = 256;
+struct TimingLog {
+  std::vector<TimingSet> sets;
+  int used = 0;
+};
+thread_local TimingLog t_timing;
+
+bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
+                    const bf_search_params* prm, void* workspace, size_t ws_bytes,
+                    hipStream_t stream) {
+  if (!bank) return fail(BF_EINVAL, "bank is NULL");
+  if (!segs || n_segs < 1) return fail(BF_EINVAL, "need at least one series");
+  bf_status st = check_params(prm);
+  if (st != BF_OK) return st;
+  const BankDev& b = bank->dev;
+  for (int32_t i = 0; i < n_segs; ++i) {
+    if (segs[i].n < b.L)
+      return fail(BF_EINVAL, "series %d has %lld samples, fewer than L = %d", i,
+                  (long long)segs[i].n, b.L);
+    if (segs[i].n > ((int64_t)1 << 31) - MAX_N_WG - b.L_pad - STRIP_SLACK)
+      return fail(BF_EINVAL, "series %d is too long", i);
+    if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
+  }
+  size_t need = table_bytes(n_segs);
+  for (int32_t i = 0; i < n_segs; ++i) need += series_ws_bytes(b, segs[i].n);
+  if (!workspace) return fail(BF_EINVAL, "workspace is NULL");
+  if (ws_bytes < need)
+    return fail(BF_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(BF_EINVAL, "workspace not 256-byte aligned");
+  if ((st = check_device_ptr(workspace, "workspace")) != BF_OK) return st;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != bank->device)
+    return fail(BF_EINVAL, "bank lives on device %d, current is %d", bank->device, dev);
+  for (int32_t i = 0; i < n_segs; ++i) {
+    if ((st = check_device_ptr(segs[i].x, "x")) != BF_OK) return st;
+    const bf_result& o = segs[i].out;
+    const void* outs[6] = {o.max_abs, o.argmax, o.spec, o.spectrum, o.hist, o.n_degenerate};
+    for (const void* q : outs)
+      if (q && (st = check_device_ptr(q, "output buffer")) != BF_OK) return st;
+  }
+
+  const SearchDev sp = make_search(b, prm);
+  std::vector<SeriesBufs> sb((size_t)n_segs);
+  char* ws = (char*)workspace;
+  size_t off = table_bytes(n_segs);
+  for (int32_t i = 0; i < n_segs; ++i) {
+    SeriesBufs& q = sb[(size_t)i];
+    series_ws_carve(b, segs[i].n, ws + off, &q);
+    off += series_ws_bytes(b, segs[i].n);
+    q.x = segs[i].x;
+    q.n = segs[i].n;
+    q.out = segs[i].out;
+  }
+  int slots = 0;
+  if ((st = device_slots(&slots)) != BF_OK) return st;
+
+  Staging* stg = acquire_staging(table_bytes(n_segs), dev, &st);
+  if (!stg) return st;
+  BatchHdr* hdr = (BatchHdr*)stg->host;
+  const TableInfo ti = fill_table(b, sp, sb.data(), n_segs, slots, hdr);
+  BatchHdr* tab_dev = (BatchHdr*)ws;
+  hipError_t e = hipMemcpyAsync(tab_dev, hdr, table_bytes(n_segs), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    release_staging(stg, false);
+    return hip_fail(e, "hipMemcpyAsync(series table)");
+  }
+  e = hipEventRecord(stg->ev, stream);
+  release_staging(stg, e == hipSuccess);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+
+  HIP_TRY(prepare_main(b, sp), "hipFuncSetAttribute(k_main)");
+  TimingSet* te = nullptr;
+  if (g_timing && (te = timing_slot(dev, &st)) == nullptr) return st;
+  const int32_t xb =
+      (int32_t)std::min<int64_t>(std::max<int64_t>((ti.max_words + 255) / 256, 1), 2048);
+  return enqueue_kernels(b, sp, tab_dev, n_segs, xb, ti.n_items, stream, te);
+}
+
+}  // namespace
+
+namespace bfly {
+
+size_t series_ws_bytes(const BankDev& b, int64_t n) {
+  const int64_t W = n - b.L + 1;
+  size_t off = 0;
+  off = align256(off + (size_t)(n + 1) * 4 * sizeof(double));
+  off = align256(off + (size_t)(n + 1) * sizeof(int32_t));
+  off = align256(off + (size_t)W * sizeof(double));
+  off = align256(off + (size_t)W * sizeof(unsigned long long));
+  off = align256(off + (size_t)b.n_bins * sizeof(unsigned long long));
   return off;
+}
+
+void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s) {
+  const int64_t W = n - b.L + 1;
+  size_t off = 0;
+  s->pre = (double*)(base + off);
+  off = align256(off + (size_t)(n + 1) * 4 * sizeof(double));
+  s->cnt = (int32_t*)(base + off);
+  off = align256(off + (size_t)(n + 1) * sizeof(int32_t));
+  s->inv_norm = (double*)(base + off);
+  off = align256(off + (size_t)W * sizeof(double));
+  s->mkey = (unsigned long long*)(base + off);
+  off = align256(off + (size_t)W * sizeof(unsigned long long));
+  s->spec_acc = (unsigned long long*)(base + off);
 }
 
 bf_status check_params(const bf_search_params* p) {
@@ -231,33 +322,17 @@ bf_status check_params(const bf_search_params* p) {
   return BF_OK;
 }
 
-// Splits the bank sweep into bin ranges so that the work items fill the device in whole
-// waves: estimated makespan = ceil(items / slots) * (tiles of the largest range), plus a
-// small per-item cost (strip fill and flushes).
-int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots) {
-  double best_cost = 1e300;
-  int32_t best_r = 1;
-  const int32_t rmax = std::min<int32_t>(b.n_bins, 4096);
-  for (int32_t r = 1; r <= rmax; ++r) {
-    const int64_t items = total_tiles * r;
-    if (items > (int64_t)0x7FFFFFFF) break;
-    int64_t max_tiles = 0;
-    // the largest range (ranges differ by at most one bin)
-    const int32_t bins = (b.n_bins + r - 1) / r;
-    const int64_t k_span = (int64_t)bins * b.n_fdot;
-    max_tiles = (k_span + TILE_K - 1) / TILE_K + 1;
-    const int64_t waves = (items + slots - 1) / slots;
-    const double cost = (double)waves * (double)max_tiles + 0.02 * (double)waves;
-    if (cost < best_cost * 0.999) {
-      best_cost = cost;
-      best_r = r;
-    }
-    if (items > 64LL * slots) break;
-  }
-  return best_r;
+SearchDev make_search(const BankDev& b, const bf_search_params* prm) {
+  SearchDev sp;
+  sp.norm = prm->norm;
+  sp.t_block = prm->t_block;
+  sp.hist_bins = prm->hist_bins;
+  sp.hist_lo = prm->hist_lo;
+  sp.hist_hi = prm->hist_hi;
+  sp.tn = choose_tn(b.precision);
+  sp.n_wg = 32 * sp.tn * WG_WAVES;
+  return sp;
 }
-
-int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
 bf_status device_slots(int* slots) {
   if (g_slots > 0) {
@@ -273,125 +348,115 @@ bf_status device_slots(int* slots) {
   return BF_OK;
 }
 
-bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
-                    const bf_search_params* prm, void* workspace, size_t ws_bytes,
-                    hipStream_t stream) {
-  if (!bank) return fail(BF_EINVAL, "bank is NULL");
-  if (!segs || n_segs < 1) return fail(BF_EINVAL, "need at least one series");
-  bf_status st = check_params(prm);
-  if (st != BF_OK) return st;
-  const BankDev& b = bank->dev;
-  std::vector<int64_t> n((size_t)n_segs);
-  for (int32_t i = 0; i < n_segs; ++i) {
-    if (segs[i].n < b.L)
-      return fail(BF_EINVAL, "series %d has %lld samples, fewer than L = %d", i,
-                  (long long)segs[i].n, b.L);
-    if (segs[i].n > ((int64_t)1 << 31) - N_WG - b.L_pad - STRIP_SLACK)
-      return fail(BF_EINVAL, "series %d is too long", i);
-    if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
-    n[(size_t)i] = segs[i].n;
+// Splits the bank sweep into bin ranges so that the work items fill the device in whole
+// waves: estimated makespan = ceil(items / slots) * (tiles of the largest range), plus a
+// small per-item cost (strip fill and flushes).
+int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots) {
+  double best_cost = 1e300;
+  int32_t best_r = 1;
+  const int32_t rmax = std::min<int32_t>(b.n_bins, 4096);
+  for (int32_t r = 1; r <= rmax; ++r) {
+    const int64_t items = total_tiles * r;
+    if (items > (int64_t)0x7FFFFFFF) break;
+    // the largest range (ranges differ by at most one bin)
+    const int32_t bins = (b.n_bins + r - 1) / r;
+    const int64_t k_span = (int64_t)bins * b.n_fdot;
+    const int64_t max_tiles = (k_span + TILE_K - 1) / TILE_K + 1;
+    const int64_t waves = (items + slots - 1) / slots;
+    const double cost = (double)waves * (double)max_tiles + 0.02 * (double)waves;
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best_r = r;
+    }
+    if (items > 64LL * slots) break;
   }
-  std::vector<SegLayout> lay;
-  const size_t need = layout(b, n.data(), n_segs, &lay);
-  if (!workspace) return fail(BF_EINVAL, "workspace is NULL");
-  if (ws_bytes < need)
-    return fail(BF_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  if (((uintptr_t)workspace & 255) != 0) return fail(BF_EINVAL, "workspace not 256-byte aligned");
-  if ((st = check_device_ptr(workspace, "workspace")) != BF_OK) return st;
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-  if (dev != bank->device) return fail(BF_EINVAL, "bank lives on device %d, current is %d",
-                                       bank->device, dev);
-  for (int32_t i = 0; i < n_segs; ++i) {
-    if ((st = check_device_ptr(segs[i].x, "x")) != BF_OK) return st;
-    const bf_result& o = segs[i].out;
-    const void* outs[6] = {o.max_abs, o.argmax, o.spec, o.spectrum, o.hist, o.n_degenerate};
-    for (const void* q : outs)
-      if (q && (st = check_device_ptr(q, "output buffer")) != BF_OK) return st;
-  }
+  return best_r;
+}
 
-  char* ws = (char*)workspace;
-  SearchDev sp;
-  sp.norm = prm->norm;
-  sp.t_block = prm->t_block;
-  sp.hist_bins = prm->hist_bins;
-  sp.hist_lo = prm->hist_lo;
-  sp.hist_hi = prm->hist_hi;
-  sp.n_segs = n_segs;
-
-  const size_t table_bytes = (size_t)n_segs * sizeof(SegDesc);
-  Staging* stg = acquire_staging(table_bytes, dev, &st);
-  if (!stg) return st;
-  SegDesc* tab = (SegDesc*)stg->host;
-  int64_t tiles = 0, max_W = 0, max_words = 0;
-  for (int32_t i = 0; i < n_segs; ++i) {
+TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s, int32_t n,
+                     int slots, BatchHdr* hdr) {
+  TableInfo ti;
+  SegDesc* tab = (SegDesc*)(hdr + 1);
+  int64_t tiles = 0;
+  for (int32_t i = 0; i < n; ++i) {
     SegDesc& d = tab[i];
-    const SegLayout& l = lay[(size_t)i];
-    d.x = segs[i].x;
-    d.n = segs[i].n;
-    d.W = segs[i].n - b.L + 1;
-    d.n_tiles = (d.W + N_WG - 1) / N_WG;
+    d.x = s[i].x;
+    d.n = s[i].n;
+    d.W = s[i].n - b.L + 1;
+    d.n_tiles = (d.W + sp.n_wg - 1) / sp.n_wg;
     d.tile0 = tiles;
     tiles += d.n_tiles;
-    d.pre = (double*)(ws + l.pre);
-    d.cnt = (int32_t*)(ws + l.cnt);
-    d.inv_norm = (double*)(ws + l.inv_norm);
-    d.mkey = (unsigned long long*)(ws + l.mkey);
-    d.spec_acc = (unsigned long long*)(ws + l.spec_acc);
-    d.max_abs = segs[i].out.max_abs;
-    d.argmax = segs[i].out.argmax;
-    d.spec = segs[i].out.spec;
-    d.spectrum = segs[i].out.spectrum;
-    d.hist = segs[i].out.hist;
-    d.n_degenerate = segs[i].out.n_degenerate;
-    d.spec_rows = (d.W + prm->t_block - 1) / prm->t_block;
-    max_W = std::max(max_W, d.W);
-    max_words = std::max(max_words, std::max(d.W, d.spec ? d.spec_rows * b.n_bins : 0));
+    d.pre = s[i].pre;
+    d.cnt = s[i].cnt;
+    d.inv_norm = s[i].inv_norm;
+    d.mkey = s[i].mkey;
+    d.spec_acc = s[i].spec_acc;
+    d.max_abs = s[i].out.max_abs;
+    d.argmax = s[i].out.argmax;
+    d.spec = s[i].out.spec;
+    d.spectrum = s[i].out.spectrum;
+    d.hist = s[i].out.hist;
+    d.n_degenerate = s[i].out.n_degenerate;
+    d.spec_rows = (d.W + sp.t_block - 1) / sp.t_block;
+    ti.max_W = std::max(ti.max_W, d.W);
+    ti.max_words = std::max(ti.max_words, std::max(d.W, d.spec ? d.spec_rows * b.n_bins : 0));
   }
-  sp.total_tiles = tiles;
-  int slots = 0;
-  if ((st = device_slots(&slots)) != BF_OK) {
-    release_staging(stg, false);
-    return st;
-  }
-  sp.n_ranges = plan_ranges(b, tiles, slots);
+  std::memset(hdr, 0, sizeof(BatchHdr));
+  hdr->n_segs = n;
+  hdr->total_tiles = tiles;
+  hdr->n_ranges = plan_ranges(b, tiles, slots);
+  hdr->n_items = tiles * hdr->n_ranges;
+  ti.n_items = hdr->n_items;
+  return ti;
+}
 
-  SegDesc* tab_dev = (SegDesc*)ws;
-  hipError_t e = hipMemcpyAsync(tab_dev, tab, table_bytes, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) {
-    release_staging(stg, false);
-    return hip_fail(e, "hipMemcpyAsync(series table)");
-  }
-  e = hipEventRecord(stg->ev, stream);
-  release_staging(stg, e == hipSuccess);
-  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-
-  TimingEvents& te = t_timing;
-  const bool timing = g_timing;
-  if (timing && (te.device != dev || !te.ev[0])) {
-    for (auto& ev : te.ev)
+TimingSet* timing_slot(int dev, bf_status* st) {
+  TimingLog& log = t_timing;
+  if (log.used >= MAX_TIMED) log.used = 0;  // drop the oldest records
+  if ((int)log.sets.size() <= log.used) log.sets.emplace_back();
+  TimingSet* te = &log.sets[(size_t)log.used];
+  if (te->device != dev) {
+    for (auto& ev : te->ev) {
       if (ev) (void)hipEventDestroy(ev);
-    for (auto& ev : te.ev) HIP_TRY(hipEventCreate(&ev), "hipEventCreate");
-    te.device = dev;
+      ev = nullptr;
+    }
+    for (auto& ev : te->ev) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) {
+        *st = hip_fail(e, "hipEventCreate");
+        te->device = -1;
+        return nullptr;
+      }
+    }
+    te->device = dev;
   }
-  te.valid = false;
-  if (timing) HIP_TRY(hipEventRecord(te.ev[0], stream), "hipEventRecord");
-  HIP_TRY(launch_zero(tab_dev, n_segs, max_words, b, sp, stream), "k_zero launch");
-  if (timing) HIP_TRY(hipEventRecord(te.ev[1], stream), "hipEventRecord");
-  HIP_TRY(launch_prefix(tab_dev, n_segs, b, sp, stream), "k_prefix launch");
-  if (timing) HIP_TRY(hipEventRecord(te.ev[2], stream), "hipEventRecord");
-  HIP_TRY(launch_norms(tab_dev, n_segs, max_W, b.L, sp.norm, stream), "k_norms launch");
-  if (timing) HIP_TRY(hipEventRecord(te.ev[3], stream), "hipEventRecord");
-  HIP_TRY(launch_main(tab_dev, b, sp, stream), "k_main launch");
-  if (timing) HIP_TRY(hipEventRecord(te.ev[4], stream), "hipEventRecord");
-  HIP_TRY(launch_finalize(tab_dev, n_segs, max_W, b, sp, stream), "k_finalize launch");
-  if (timing) {
-    HIP_TRY(hipEventRecord(te.ev[5], stream), "hipEventRecord");
-    te.valid = true;
-  }
+  ++log.used;
+  return te;
+}
+
+// x_blocks: blocks per series of the grid-stride kernels (any value >= 1 is correct);
+// main_blocks: work-groups of the contraction kernel (n_items for one item each).
+bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr* table_dev,
+                          int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                          hipStream_t stream, TimingSet* te) {
+  const int32_t xb = x_blocks > 0 ? x_blocks : 1;
+  if (te) HIP_TRY(hipEventRecord(te->ev[0], stream), "hipEventRecord");
+  HIP_TRY(launch_zero(table_dev, seg_slots, xb, b, sp, stream), "k_zero launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[1], stream), "hipEventRecord");
+  HIP_TRY(launch_prefix(table_dev, seg_slots, stream), "k_prefix launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[2], stream), "hipEventRecord");
+  HIP_TRY(launch_norms(table_dev, seg_slots, xb, b.L, sp.norm, stream), "k_norms launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[3], stream), "hipEventRecord");
+  HIP_TRY(launch_main(table_dev, main_blocks, b, sp, stream), "k_main launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[4], stream), "hipEventRecord");
+  HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp, stream), "k_finalize launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[5], stream), "hipEventRecord");
   return BF_OK;
 }
 
+}  // namespace bfly
+
+namespace {
 }  // namespace
 
 // =======================================================================================
@@ -405,7 +470,7 @@ bf_status bf_bank_bytes(const bf_bank_desc* desc, size_t* bytes) {
     GridDev g;
     BankDev b;
     fill_geometry(desc, &g, &b);
-    *bytes = bank_data_bytes(b) + 256;
+    *bytes = bank_total_bytes(b);
     return BF_OK;
   } catch (...) {
     return fail(BF_ENOMEM, "internal error");
@@ -422,7 +487,7 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     GridDev g;
     BankDev b;
     fill_geometry(desc, &g, &b);
-    const size_t need = bank_data_bytes(b) + 256;
+    const size_t need = bank_total_bytes(b);
     if (!dev_mem) return fail(BF_EINVAL, "dev_mem is NULL");
     if (dev_bytes < need) return fail(BF_EINVAL, "dev_mem too small: %zu < %zu", dev_bytes, need);
     if (((uintptr_t)dev_mem & 255) != 0) return fail(BF_EINVAL, "dev_mem not 256-byte aligned");
@@ -430,7 +495,7 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_bank_gen(g, b, dev_mem, s), "k_bank_gen launch");
     unsigned int bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, (char*)dev_mem + bank_data_bytes(b), sizeof bad,
+    HIP_TRY(hipMemcpyAsync(&bad, (char*)dev_mem + bank_data_bytes(b) + bank_exp_bytes(b), sizeof bad,
                            hipMemcpyDeviceToHost, s),
             "hipMemcpyAsync(bank check)");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(bank)");
@@ -441,6 +506,8 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     bk->grid = g;
     bk->dev = b;
     bk->dev.data = dev_mem;
+    bk->dev.texp = b.precision == P_FP8 ? (const int32_t*)((char*)dev_mem + bank_data_bytes(b))
+                                        : nullptr;
     HIP_TRY(hipGetDevice(&bk->device), "hipGetDevice");
     *out = bk;
     return BF_OK;
@@ -482,7 +549,9 @@ bf_status bf_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_t n_se
       if (n[i] < bank->dev.L)
         return fail(BF_EINVAL, "series %d has %lld samples, fewer than L = %d", i,
                     (long long)n[i], bank->dev.L);
-    *bytes = layout(bank->dev, n, n_segs, nullptr);
+    size_t total = table_bytes(n_segs);
+    for (int32_t i = 0; i < n_segs; ++i) total += series_ws_bytes(bank->dev, n[i]);
+    *bytes = total;
     return BF_OK;
   } catch (...) {
     return fail(BF_ENOMEM, "internal error");
@@ -520,16 +589,22 @@ bf_status bf_set_timing(int32_t enable) {
   return BF_OK;
 }
 
-bf_status bf_kernel_times(double* ms) {
+bf_status bf_kernel_times(double* ms, int32_t* n_searches) {
   if (!ms) return fail(BF_EINVAL, "ms is NULL");
-  TimingEvents& te = t_timing;
-  if (!te.valid) return fail(BF_EAGAIN, "no timed search on this thread");
-  HIP_TRY(hipEventSynchronize(te.ev[5]), "hipEventSynchronize");
-  for (int i = 0; i < 5; ++i) {
-    float v = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&v, te.ev[i], te.ev[i + 1]), "hipEventElapsedTime");
-    ms[i] = (double)v;
+  TimingLog& log = t_timing;
+  if (log.used == 0) return fail(BF_EAGAIN, "no timed search on this thread");
+  for (int i = 0; i < 5; ++i) ms[i] = 0.0;
+  for (int k = 0; k < log.used; ++k) {
+    TimingSet& t = log.sets[(size_t)k];
+    HIP_TRY(hipEventSynchronize(t.ev[5]), "hipEventSynchronize");
+    for (int i = 0; i < 5; ++i) {
+      float v = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&v, t.ev[i], t.ev[i + 1]), "hipEventElapsedTime");
+      ms[i] += (double)v;
+    }
   }
+  if (n_searches) *n_searches = log.used;
+  log.used = 0;
   return BF_OK;
 }
 
@@ -539,7 +614,8 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   int64_t tiles = 0;
   for (int32_t i = 0; i < n_segs; ++i) {
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
-    tiles += (n[i] - bank->dev.L + 1 + N_WG - 1) / N_WG;
+    const int64_t n_wg = 32 * (int64_t)choose_tn(bank->dev.precision) * WG_WAVES;
+    tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
   }
   int slots = 0;
   bf_status st = device_slots(&slots);

@@ -8,18 +8,17 @@
 namespace bfly {
 
 // ---- tile geometry of the contraction kernel -------------------------------------------
-// A work-group of 4 waves owns N_WG consecutive offsets; each wave owns TN blocks of 32
-// offsets.  All four waves sweep the same templates, TM blocks of 32 per step, and the
-// taps in chunks of KCH.
+// A work-group of 4 waves owns 4 * 32 * tn consecutive offsets; each wave owns tn blocks
+// of 32 offsets (tn = 4 or 8, chosen per search).  All four waves sweep the same
+// templates, TM blocks of 32 per step, and the taps in chunks of KCH.
 constexpr int WAVE = 64;
 constexpr int WG_WAVES = 4;
 constexpr int WG_THREADS = WAVE * WG_WAVES;
 constexpr int TM = 2;                         // 32-template blocks per template tile
 constexpr int TILE_K = 32 * TM;               // templates per template tile
-constexpr int TN = 4;                         // 32-offset blocks per wave
-constexpr int N_WAVE = 32 * TN;               // offsets per wave
-constexpr int N_WG = N_WAVE * WG_WAVES;       // offsets per work item
-constexpr int KCH = 16;                       // taps per chunk (L_pad is a multiple of 2*KCH)
+constexpr int MAX_N_WG = 32 * 8 * WG_WAVES;  // offsets per work item at tn = 8
+constexpr int KCH = 16;                       // taps per chunk, FP32 and BF16 forms
+constexpr int KCH_FP8 = 64;                   // taps per chunk, FP8 form
 constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG + L_pad
 constexpr int MAX_L = 8192;
 constexpr int MAX_HIST_BINS = 4096;
@@ -27,13 +26,16 @@ constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectru
 
 enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2 };
 
+// Taps per K-loop chunk; L_pad is a multiple of twice this.
+constexpr int chunk_taps(int precision) { return precision == P_FP8 ? KCH_FP8 : KCH; }
+
 // Per-series table entry, resident in the workspace (device).
 struct SegDesc {
   const float* x;
   int64_t n;
   int64_t W;
   int64_t tile0;        // first global offset tile of this series
-  int64_t n_tiles;      // ceil(W / N_WG)
+  int64_t n_tiles;      // ceil(W / n_wg)
   double* pre;          // [n+1][4] prefix sums: S1 (hi, lo), S2 (hi, lo)
   int32_t* cnt;         // [n+1] prefix count of non-finite samples
   double* inv_norm;     // [W] 1/sqrt(E), 0 for degenerate windows
@@ -48,15 +50,32 @@ struct SegDesc {
   int64_t spec_rows;    // ceil(W / t_block)
 };
 
+// Header of a batch table in device memory: the table is [BatchHdr][SegDesc x n_segs].  The
+// kernels read the batch sizes from it, so one captured launch sequence (grids sized for the
+// largest batch, the contraction kernel looping over its work items) serves any batch.
+struct BatchHdr {
+  int32_t n_segs;
+  int32_t n_ranges;     // bin ranges the bank sweep is split into
+  int64_t total_tiles;  // sum of n_tiles over the series
+  int64_t n_items;      // total_tiles * n_ranges
+  int64_t reserved[5];
+};
+static_assert(sizeof(BatchHdr) == 64, "BatchHdr layout");
+
+__host__ __device__ inline const SegDesc* hdr_segs(const BatchHdr* h) {
+  return reinterpret_cast<const SegDesc*>(h + 1);
+}
+
 // The bank as the kernels see it (passed by value).
 struct BankDev {
   const void* data;     // tile layout, see bank_gen
+  const int32_t* texp;  // FP8: per-template power-of-two exponent e_k (codes hold h * 2^e_k)
   int64_t K;            // local templates
   int64_t K_pad;        // multiple of TILE_K
   int64_t k_offset;     // global index of local template 0
   int32_t L;
   int32_t L_pad;        // multiple of KCH
-  int32_t n_chunks;     // L_pad / KCH
+  int32_t n_chunks;     // L_pad / chunk_taps(precision)
   int32_t n_fdot;       // templates per spectrogram bin
   int32_t n_bins;
   int32_t precision;
@@ -72,24 +91,38 @@ struct SearchDev {
   int32_t norm;
   int32_t t_block;
   int32_t hist_bins;
-  int32_t n_ranges;     // bin ranges the bank sweep is split into
+  int32_t tn;           // 32-offset blocks per wave (4 or 8)
+  int32_t n_wg;         // offsets per work item = 4 * 32 * tn
   double hist_lo, hist_hi;
-  int64_t total_tiles;  // sum of n_tiles over the series
-  int32_t n_segs;
 };
 
+// Bytes of the quantised templates, of the FP8 exponents, and of the whole bank allocation
+// (templates, exponents, then a 256-byte status word).
+inline size_t bank_data_bytes(const BankDev& b) {
+  return (size_t)b.K_pad * (size_t)b.L_pad * (b.precision == P_FP8 ? 1 : 4);
+}
+inline size_t bank_exp_bytes(const BankDev& b) {
+  return b.precision == P_FP8 ? (((size_t)b.K_pad * 4 + 255) & ~(size_t)255) : 0;
+}
+inline size_t bank_total_bytes(const BankDev& b) {
+  return bank_data_bytes(b) + bank_exp_bytes(b) + 256;
+}
+
 // ---- launchers (bfly_kernels.hip); each returns the launch's hipError_t ----------------
+// Grid sizes: seg_slots = series the grids cover (>= hdr->n_segs), x_blocks = blocks per
+// series of the grid-stride kernels, main_blocks = work-groups of the contraction kernel
+// (each loops over items blockIdx.x, blockIdx.x + main_blocks, ... < hdr->n_items).
 hipError_t launch_bank_gen(const GridDev& g, const BankDev& b, void* dst, hipStream_t s);
-hipError_t launch_zero(const SegDesc* segs_dev, int32_t n_segs, int64_t max_words,
+hipError_t launch_zero(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
                        const BankDev& b, const SearchDev& p, hipStream_t s);
-hipError_t launch_prefix(const SegDesc* segs_dev, int32_t n_segs, const BankDev& b,
-                         const SearchDev& p, hipStream_t s);
-hipError_t launch_norms(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W, int L,
+hipError_t launch_prefix(const BatchHdr* hdr, int32_t seg_slots, hipStream_t s);
+hipError_t launch_norms(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks, int L,
                         int norm, hipStream_t s);
-hipError_t launch_main(const SegDesc* segs_dev, const BankDev& b, const SearchDev& p,
-                       hipStream_t s);
-hipError_t launch_finalize(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W,
+hipError_t prepare_main(const BankDev& b, const SearchDev& p);
+hipError_t launch_main(const BatchHdr* hdr, int64_t main_blocks, const BankDev& b,
+                       const SearchDev& p, hipStream_t s);
+hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
                            const BankDev& b, const SearchDev& p, hipStream_t s);
-size_t main_lds_bytes(int precision, int L_pad);
+size_t main_lds_bytes(int precision, int L_pad, int n_wg);
 
 }  // namespace bfly

@@ -24,6 +24,7 @@ namespace bfly {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------------------
 // Small numeric helpers.
@@ -86,11 +87,15 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // BF16X3 layout, per (b, c): plane (hi, lo) x 64 lanes x 8 bf16, lane l = h*32 + m holding
 //   taps 16c + 8h + i (i = 0..7) of template 32b + m -- the A operand of one
 //   v_mfma_f32_32x32x16_bf16 step.
+// FP8 layout, per (b, 64-tap chunk c): 64 lanes x 32 e4m3 codes, lane l = h*32 + m holding
+//   taps 64c + 32h + i (i = 0..31) of template 32b + m -- the A operand of one
+//   v_mfma_scale_f32_32x32x64_f8f6f4; template k is stored as h_k * 2^e_k with e_k the
+//   largest exponent keeping max |h_k| * 2^e_k <= 448, and e_k is kept in texp[k].
 // Padding templates (k >= K) and padding taps (n >= L) are zero.  The word after the bank
 // counts templates whose centred norm vanished (they cannot be normalised).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* dst,
-                                                  unsigned int* bad) {
+                                                  int32_t* texp, unsigned int* bad) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * 4 + wave;
   if (k >= b.K_pad) return;
@@ -123,14 +128,26 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
   }
   const int64_t blk = k >> 5;
   const int m = (int)(k & 31);
+  int e8 = 0;
+  if (b.precision == P_FP8) {
+    double mx = 0.0;
+    if (real)
+      for (int n = lane; n < b.L; n += 64)
+        mx = fmax(mx, fabs((chirp_sample(g.fs, f0, fdot, n) - mu) / nrm));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    e8 = mx > 0.0 ? (int)floor(log2(448.0 / mx)) : 0;
+    if (lane == 0) texp[k] = e8;
+  }
   for (int n = lane; n < b.L_pad; n += 64) {
     const double h = (real && n < b.L) ? (chirp_sample(g.fs, f0, fdot, n) - mu) / nrm : 0.0;
-    const int c = n >> 4, r = n & 15;
     if (b.precision == P_FP32) {
+      const int c = n >> 4, r = n & 15;
       const int ln = (r & 1) * 32 + m, s = r >> 1;
       float* out = (float*)dst;
       out[(((int64_t)blk * b.n_chunks + c) * 64 + ln) * 8 + s] = (float)h;
-    } else {
+    } else if (b.precision == P_BF16X3) {
+      const int c = n >> 4, r = n & 15;
       const int ln = (r >> 3) * 32 + m, i = r & 7;
       const double hi = round_bf16_d(h);
       const double lo = round_bf16_d(h - hi);
@@ -138,17 +155,24 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
       const int64_t base = ((int64_t)blk * b.n_chunks + c) * 2;
       out[((base + 0) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)hi) >> 16);
       out[((base + 1) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)lo) >> 16);
+    } else {
+      const int c = n >> 6, r = n & 63;
+      const int ln = (r >> 5) * 32 + m, i = r & 31;
+      const float v = (float)ldexp(h, e8);   // |v| <= 448 by the choice of e8
+      const int code = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF;
+      uint8_t* out = (uint8_t*)dst;
+      out[(((int64_t)blk * b.n_chunks + c) * 64 + ln) * 32 + i] = (uint8_t)code;
     }
   }
 }
 
 hipError_t launch_bank_gen(const GridDev& g, const BankDev& b, void* dst, hipStream_t s) {
-  const size_t bank_bytes = (size_t)b.K_pad * (size_t)b.L_pad * 4;
-  unsigned int* bad = (unsigned int*)((char*)dst + bank_bytes);
+  int32_t* texp = (int32_t*)((char*)dst + bank_data_bytes(b));
+  unsigned int* bad = (unsigned int*)((char*)dst + bank_data_bytes(b) + bank_exp_bytes(b));
   hipError_t e = hipMemsetAsync(bad, 0, 256, s);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((b.K_pad + 3) / 4);
-  hipLaunchKernelGGL(k_bank_gen, dim3(grid), dim3(256), 0, s, g, b, dst, bad);
+  hipLaunchKernelGGL(k_bank_gen, dim3(grid), dim3(256), 0, s, g, b, dst, texp, bad);
   return hipGetLastError();
 }
 
@@ -156,9 +180,10 @@ hipError_t launch_bank_gen(const GridDev& g, const BankDev& b, void* dst, hipStr
 // Clearing: running maxima, spectrogram, spectrum sums, histogram, degenerate count.
 // grid = (X, n_segs); each series clears its own buffers with a grid-stride loop.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_zero(const SegDesc* __restrict__ segs, BankDev b,
+__global__ __launch_bounds__(256) void k_zero(const BatchHdr* __restrict__ hdr, BankDev b,
                                               SearchDev p) {
-  const SegDesc& sg = segs[blockIdx.y];
+  if ((int)blockIdx.y >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < sg.W; i += stride) sg.mkey[i] = 0ull;
@@ -172,13 +197,10 @@ __global__ __launch_bounds__(256) void k_zero(const SegDesc* __restrict__ segs, 
   if (sg.n_degenerate && t0 == 0) sg.n_degenerate[0] = 0;
 }
 
-hipError_t launch_zero(const SegDesc* segs_dev, int32_t n_segs, int64_t max_words,
+hipError_t launch_zero(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
                        const BankDev& b, const SearchDev& p, hipStream_t s) {
-  int64_t blocks = (max_words + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
-                     segs_dev, b, p);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)x_blocks, (unsigned)seg_slots), dim3(256), 0, s,
+                     hdr, b, p);
   return hipGetLastError();
 }
 
@@ -187,8 +209,9 @@ hipError_t launch_zero(const SegDesc* segs_dev, int32_t n_segs, int64_t max_word
 // carrying double-double sums of x and x^2 (non-finite samples count as 0 and are
 // counted separately).  pre[i] holds the sums over x[0..i).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_prefix(const SegDesc* __restrict__ segs) {
-  const SegDesc& sg = segs[blockIdx.x];
+__global__ __launch_bounds__(1024) void k_prefix(const BatchHdr* __restrict__ hdr) {
+  if ((int)blockIdx.x >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.x];
   __shared__ dd w1[16], w2[16];
   __shared__ int wc[16];
   __shared__ dd c1s, c2s;
@@ -262,9 +285,8 @@ __global__ __launch_bounds__(1024) void k_prefix(const SegDesc* __restrict__ seg
   }
 }
 
-hipError_t launch_prefix(const SegDesc* segs_dev, int32_t n_segs, const BankDev&,
-                         const SearchDev&, hipStream_t s) {
-  hipLaunchKernelGGL(k_prefix, dim3((unsigned)n_segs), dim3(1024), 0, s, segs_dev);
+hipError_t launch_prefix(const BatchHdr* hdr, int32_t seg_slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_prefix, dim3((unsigned)seg_slots), dim3(1024), 0, s, hdr);
   return hipGetLastError();
 }
 
@@ -274,9 +296,10 @@ hipError_t launch_prefix(const SegDesc* segs_dev, int32_t n_segs, const BankDev&
 // double-double so that windows with a large mean keep their small variance.  Raw: E = D2.
 // Degenerate (inv_norm = 0): a non-finite sample, R = D2 = 0, or E <= 1e-12 R.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_norms(const SegDesc* __restrict__ segs, int L,
+__global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr, int L,
                                                int norm) {
-  const SegDesc& sg = segs[blockIdx.y];
+  if ((int)blockIdx.y >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tau < sg.W;
        tau += stride) {
@@ -306,12 +329,12 @@ __global__ __launch_bounds__(256) void k_norms(const SegDesc* __restrict__ segs,
 // ---------------------------------------------------------------------------------------
 // The contraction with the fused reductions.
 //
-// Work item = (series, offset tile of N_WG offsets, bin range).  Items are numbered
+// Work item = (series, offset tile of n_wg = 128*NB offsets, bin range).  Items are numbered
 // range-major, so the work-groups resident at any time sweep the same templates and share
-// them through L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + N_WG + L_pad) (zero
+// them through L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + n_wg + L_pad) (zero
 // past the end; non-finite samples as 0 -- their windows are degenerate and discarded),
 // then each wave sweeps the item's template tiles: for each tile, a full K-loop over the
-// taps into TM x TN accumulators of 32 x 32, then the epilogue.
+// taps into TM x NB accumulators of 32 x 32, then the epilogue.
 //
 // MFMA fragments (64 lanes, lane = h*32 + n):
 //   FP32  v_mfma_f32_32x32x2_f32: A lane holds h_k[kk + h] of template row n,
@@ -322,9 +345,9 @@ __global__ __launch_bounds__(256) void k_norms(const SegDesc* __restrict__ segs,
 //         8-byte-aligned LDS reads whatever tau is.  hi*hi + hi*lo + lo*hi are accumulated.
 //   Output lane holds column n, rows 8g + 4h + i4 (g, i4 < 4) in accumulator 4g + i4.
 // ---------------------------------------------------------------------------------------
-size_t main_lds_bytes(int precision, int L_pad) {
-  const size_t S = (size_t)N_WG + (size_t)L_pad + STRIP_SLACK;
-  return precision == P_FP32 ? S * 4 : S * 16;
+size_t main_lds_bytes(int precision, int L_pad, int n_wg) {
+  const size_t S = (size_t)n_wg + (size_t)L_pad + STRIP_SLACK;
+  return precision == P_FP32 ? S * 4 : precision == P_FP8 ? S * 8 : S * 16;
 }
 
 struct ItemCtx {
@@ -343,6 +366,10 @@ template <>
 struct AFrag<P_BF16X3> {
   uint4 v[TM][2];     // [block][plane hi/lo]
 };
+template <>
+struct AFrag<P_FP8> {
+  uint4 v[TM][2];     // 32 e4m3 codes per lane per block per chunk
+};
 
 template <int PREC>
 __device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t blk0, int c,
@@ -355,13 +382,21 @@ __device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 1];
     }
-  } else {
+  } else if constexpr (PREC == P_BF16X3) {
     const uint4* A = (const uint4*)bank;
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
       const int64_t idx = (((blk0 + t) * nchunks + c) * 2) * 64 + lane;
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 64];
+    }
+  } else {
+    const uint4* A = (const uint4*)bank;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int64_t idx = (((blk0 + t) * nchunks + c) * 64 + lane) * 2;
+      f.v[t][0] = A[idx];
+      f.v[t][1] = A[idx + 1];
     }
   }
 }
@@ -371,19 +406,23 @@ __device__ __forceinline__ float f4get(const float4& v, int i) {
 }
 
 // B operand fragments of one 16-tap chunk, read from the LDS strip.
-template <int PREC>
+template <int PREC, int NB>
 struct BFrag;
-template <>
-struct BFrag<P_FP32> {
-  float v[8][TN];     // [2-tap step][offset block]
+template <int NB>
+struct BFrag<P_FP32, NB> {
+  float v[8][NB];     // [2-tap step][offset block]
 };
-template <>
-struct BFrag<P_BF16X3> {
-  uint4 v[TN][2];     // [offset block][plane hi/lo]
+template <int NB>
+struct BFrag<P_BF16X3, NB> {
+  uint4 v[NB][2];     // [offset block][plane hi/lo]
+};
+template <int NB>
+struct BFrag<P_FP8, NB> {
+  uint4 v[NB][2];     // [offset block][32 codes]
 };
 
-template <int PREC>
-__device__ __forceinline__ void load_b(BFrag<PREC>& f, const char* lds, int off_w, int c,
+template <int PREC, int NB>
+__device__ __forceinline__ void load_b(BFrag<PREC, NB>& f, const char* lds, int off_w, int c,
                                        int n, int h, int plane_bytes) {
   if constexpr (PREC == P_FP32) {
     const float* sx = (const float*)lds;
@@ -391,10 +430,24 @@ __device__ __forceinline__ void load_b(BFrag<PREC>& f, const char* lds, int off_
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) f.v[s][j] = sx[p0 + 32 * j + 2 * s];
+      for (int j = 0; j < NB; ++j) f.v[s][j] = sx[p0 + 32 * j + 2 * s];
+  } else if constexpr (PREC == P_FP8) {
+    // 8 copies shifted by 0..7 samples, interleaved per 8-sample cell (8 bytes each):
+    // a lane's 32 consecutive codes are four 8-byte-aligned reads.
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int p = off_w + 32 * j + n + 64 * c + 32 * h;
+      const int addr = (p >> 3) * 64 + (p & 7) * 8;
+      const uint2 u0 = *(const uint2*)(lds + addr);
+      const uint2 u1 = *(const uint2*)(lds + addr + 64);
+      const uint2 u2 = *(const uint2*)(lds + addr + 128);
+      const uint2 u3 = *(const uint2*)(lds + addr + 192);
+      f.v[j][0] = make_uint4(u0.x, u0.y, u1.x, u1.y);
+      f.v[j][1] = make_uint4(u2.x, u2.y, u3.x, u3.y);
+    }
   } else {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
+    for (int j = 0; j < NB; ++j) {
       const int p = off_w + 32 * j + n + 16 * c + 8 * h;
       const int addr = (p >> 2) * 32 + (p & 3) * 8;
 #pragma unroll
@@ -408,17 +461,35 @@ __device__ __forceinline__ void load_b(BFrag<PREC>& f, const char* lds, int off_
 }
 
 // The MFMAs of one 16-tap chunk.
-template <int PREC>
-__device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][TN], const AFrag<PREC>& a,
-                                          const BFrag<PREC>& bf) {
-  if constexpr (PREC == P_FP32) {
+struct U8 {
+  uint4 a, b;
+};
+
+template <int PREC, int NB>
+__device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][NB], const AFrag<PREC>& a,
+                                          const BFrag<PREC, NB>& bf, const int (&sa)[TM],
+                                          int sb) {
+  if constexpr (PREC == P_FP8) {
+    // e4m3 x e4m3, with the E8M0 scales 2^-e_k (per template row, per lane) and 2^-e_x
+    // (per strip) undoing the power-of-two scaling of both operands.
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const i32x8 av = __builtin_bit_cast(i32x8, (U8{a.v[t][0], a.v[t][1]}));
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const i32x8 bv = __builtin_bit_cast(i32x8, (U8{bf.v[j][0], bf.v[j][1]}));
+        acc[t][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[t][j], 0, 0, 0,
+                                                                    sa[t], 0, sb);
+      }
+    }
+  } else if constexpr (PREC == P_FP32) {
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
         const float av = f4get(a.v[t][s >> 2], s & 3);
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < NB; ++j)
           acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf.v[s][j], acc[t][j], 0, 0, 0);
       }
   } else {
@@ -430,7 +501,7 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][TN], const AFrag<PRE
       for (int t = 0; t < TM; ++t) {
         const bf16x8 av = __builtin_bit_cast(bf16x8, a.v[t][pa]);
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
+        for (int j = 0; j < NB; ++j) {
           const bf16x8 b = __builtin_bit_cast(bf16x8, bf.v[j][pb]);
           acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b, acc[t][j], 0, 0, 0);
         }
@@ -439,14 +510,15 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][TN], const AFrag<PRE
   }
 }
 
-// Spectrogram / spectrum flush of the current bin for this wave's TN x 32 offsets.
+// Spectrogram / spectrum flush of the current bin for this wave's NB x 32 offsets.
+template <int NB>
 __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
-                                          const SearchDev& p, int bin, const float (&binmax)[TN],
-                                          const double (&inv)[TN], int64_t tau_w0, int n,
+                                          const SearchDev& p, int bin, const float (&binmax)[NB],
+                                          const double (&inv)[NB], int64_t tau_w0, int n,
                                           int h, int lane) {
   unsigned long long fix = 0ull;
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const float v = fmaxf(binmax[j], __shfl_xor(binmax[j], 32, 64));
     const int64_t tau = tau_w0 + 32 * j + n;
     if (h == 0 && tau < sg.W && inv[j] > 0.0) {
@@ -468,39 +540,76 @@ __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
   if (lane == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
 }
 
-template <int PREC>
-__global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restrict__ segs,
-                                                        BankDev b, SearchDev p) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
+// One work item: strip fill, template sweep, flushes.
+template <int PREC, int NB>
+__device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int64_t item,
+                                          const BankDev& b, const SearchDev& p, char* lds) {
+  const SegDesc* segs = hdr_segs(hdr);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = lane & 31, h = lane >> 5;
+  const int64_t total_tiles = hdr->total_tiles;
+  const int n_ranges = hdr->n_ranges;
 
   // ---- which item ----
-  const int64_t item = blockIdx.x;
-  const int r = (int)(item / p.total_tiles);
-  const int64_t tt = item % p.total_tiles;
-  int lo = 0, hi = p.n_segs - 1;
+  const int r = (int)(item / total_tiles);
+  const int64_t tt = item % total_tiles;
+  int lo = 0, hi = hdr->n_segs - 1;
   while (lo < hi) {  // last series with tile0 <= tt
     const int mid = (lo + hi + 1) >> 1;
     if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
   }
   const SegDesc& sg = segs[lo];
-  const int64_t tau0 = (tt - sg.tile0) * N_WG;
-  const int b_lo = (int)((int64_t)r * b.n_bins / p.n_ranges);
-  const int b_hi = (int)((int64_t)(r + 1) * b.n_bins / p.n_ranges);
+  const int64_t tau0 = (tt - sg.tile0) * (32 * NB * WG_WAVES);
+  const int b_lo = (int)((int64_t)r * b.n_bins / n_ranges);
+  const int b_hi = (int)((int64_t)(r + 1) * b.n_bins / n_ranges);
   const int64_t k_lo = (int64_t)b_lo * b.n_fdot;
   const int64_t k_hi = (int64_t)b_hi * b.n_fdot;
   const int64_t tile_lo = k_lo / TILE_K;
   const int64_t tile_hi = (k_hi + TILE_K - 1) / TILE_K;
 
   // ---- strip fill ----
-  const int S = N_WG + b.L_pad + STRIP_SLACK;  // multiple of 4
+  const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
+  int sb = 127;   // FP8: E8M0 scale undoing the strip's 2^e_x
   if constexpr (PREC == P_FP32) {
     float* sx = (float*)lds;
     for (int i = tid; i < S; i += WG_THREADS) {
       const int64_t gi = tau0 + i;
       float v = gi < sg.n ? sg.x[gi] : 0.0f;
       sx[i] = isfinite(v) ? v : 0.0f;
+    }
+  } else if constexpr (PREC == P_FP8) {
+    // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= 448
+    __shared__ float wmax[WG_WAVES];
+    float mx = 0.0f;
+    for (int i = tid; i < S; i += WG_THREADS) {
+      const int64_t gi = tau0 + i;
+      const float v = gi < sg.n ? sg.x[gi] : 0.0f;
+      if (isfinite(v)) mx = fmaxf(mx, fabsf(v));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) wmax[wave] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    int ex = mx > 0.0f ? (int)floorf(log2f(448.0f / mx)) : 0;
+    ex = ex < -100 ? -100 : (ex > 100 ? 100 : ex);
+    while (ex > -100 && ldexpf(mx, ex) > 448.0f) --ex;   // guard log2f rounding
+    sb = 127 - ex;
+    // cell (q, c): codes of x[tau0 + 8q + c + e] * 2^e_x, e = 0..7
+    for (int t = tid; t < S; t += WG_THREADS) {
+      const int q = t >> 3, c = t & 7;
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t gi = tau0 + 8 * q + c + e;
+        float u = gi < sg.n ? sg.x[gi] : 0.0f;
+        v[e] = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+      }
+      int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+      w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w0, true);
+      int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
+      w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], w1, true);
+      *(uint2*)(lds + t * 8) = make_uint2((unsigned)w0, (unsigned)w1);
     }
   } else {
     // cell (q, c) of plane pl: samples x[tau0 + 4q + c + e], e = 0..3, as bf16 hi / lo.
@@ -525,20 +634,20 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
   }
   __syncthreads();
 
-  const int64_t tau_w0 = tau0 + (int64_t)wave * N_WAVE;
-  const int off_w = wave * N_WAVE;
+  const int64_t tau_w0 = tau0 + (int64_t)wave * (32 * NB);
+  const int off_w = wave * (32 * NB);
   const int plane_bytes = S * 8;
 
-  double inv[TN];
+  double inv[NB];
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const int64_t tau = tau_w0 + 32 * j + n;
     inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
   }
-  float best[TN], binmax[TN];
-  int bestk[TN];
+  float best[NB], binmax[NB];
+  int bestk[NB];
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
+  for (int j = 0; j < NB; ++j) {
     best[j] = -1.0f;
     bestk[j] = -1;
     binmax[j] = 0.0f;
@@ -547,39 +656,43 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
   const int nfd = b.n_fdot;
 
   for (int64_t kt = tile_lo; kt < tile_hi; ++kt) {
-    f32x16 acc[TM][TN];
+    f32x16 acc[TM][NB];
 #pragma unroll
     for (int t = 0; t < TM; ++t)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[t][j] = (f32x16){};
+      for (int j = 0; j < NB; ++j) acc[t][j] = (f32x16){};
 
     const int64_t blk0 = kt * TM;
+    int sa[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+      sa[t] = PREC == P_FP8 ? 127 - b.texp[(blk0 + t) * 32 + n] : 127;
     // Software pipeline over chunk pairs (n_chunks is even): while the MFMAs of chunk c
     // run, the template fragments of chunk c+1 and the strip fragments of chunk c+1 are in
     // flight.  Scheduling barriers keep the compiler from sinking the loads next to their
     // uses.  The prefetches past the last chunk re-read a valid chunk and are unused.
     const int nc = b.n_chunks;
     AFrag<PREC> a0, a1;
-    BFrag<PREC> b0, b1;
+    BFrag<PREC, NB> b0, b1;
     __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
     __builtin_amdgcn_sched_barrier(0);
     load_a<PREC>(a0, b.data, blk0, 0, nc, lane);
     __builtin_amdgcn_sched_barrier(0);
-    load_b<PREC>(b0, lds, off_w, 0, n, h, plane_bytes);
+    load_b<PREC, NB>(b0, lds, off_w, 0, n, h, plane_bytes);
     __builtin_amdgcn_sched_barrier(0);
     for (int c = 0; c < nc; c += 2) {
       load_a<PREC>(a1, b.data, blk0, c + 1, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
-      load_b<PREC>(b1, lds, off_w, c + 1, n, h, plane_bytes);
+      load_b<PREC, NB>(b1, lds, off_w, c + 1, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
-      mma_chunk<PREC>(acc, a0, b0);
+      mma_chunk<PREC, NB>(acc, a0, b0, sa, sb);
       __builtin_amdgcn_sched_barrier(0);
       const int c2 = c + 2 < nc ? c + 2 : nc - 1;
       load_a<PREC>(a0, b.data, blk0, c2, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
-      load_b<PREC>(b0, lds, off_w, c2, n, h, plane_bytes);
+      load_b<PREC, NB>(b0, lds, off_w, c2, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
-      mma_chunk<PREC>(acc, a1, b1);
+      mma_chunk<PREC, NB>(acc, a1, b1, sa, sb);
       __builtin_amdgcn_sched_barrier(0);
     }
 
@@ -591,27 +704,35 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
     if (r_lo == 0 && r_hi == TILE_K && bA == bB) {
       // whole tile owned and inside one bin
       if (bA != cur_bin) {
-        if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+        if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
         cur_bin = bA;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) binmax[j] = 0.0f;
+        for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
       }
+      // per offset column: tree maximum of the lane's 32 rows, then the lowest row that
+      // reaches it; one column at a time keeps few accumulators live in VGPRs.
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
+      for (int j = 0; j < NB; ++j) {
+        float mx = 0.0f;
 #pragma unroll
         for (int t = 0; t < TM; ++t)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const float a = fabsf(acc[t][j][v]);
-            const bool gt = a > best[j];
-            best[j] = gt ? a : best[j];
-            bestk[j] = gt ? (int)kbase + 32 * t + 8 * (v >> 2) + 4 * h + (v & 3) : bestk[j];
-            binmax[j] = fmaxf(binmax[j], a);
-          }
+          for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fabsf(acc[t][j][v]));
+        int row = 0;
+#pragma unroll
+        for (int t = TM - 1; t >= 0; --t)
+#pragma unroll
+          for (int v = 15; v >= 0; --v)
+            row = fabsf(acc[t][j][v]) == mx ? 32 * t + 8 * (v >> 2) + 4 * h + (v & 3) : row;
+        const bool gt = mx > best[j];
+        best[j] = gt ? mx : best[j];
+        bestk[j] = gt ? (int)kbase + row : bestk[j];
+        binmax[j] = fmaxf(binmax[j], mx);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int t = 0; t < TM; ++t)
 #pragma unroll
@@ -624,16 +745,16 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
           }
       for (int bn = bA; bn <= bB; ++bn) {
         if (bn != cur_bin) {
-          if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+          if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
           cur_bin = bn;
 #pragma unroll
-          for (int j = 0; j < TN; ++j) binmax[j] = 0.0f;
+          for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
         }
         const int64_t e_lo = (int64_t)bn * nfd - kbase, e_hi = (int64_t)(bn + 1) * nfd - kbase;
         const int q_lo = (int)(e_lo > r_lo ? e_lo : r_lo);
         const int q_hi = (int)(e_hi < r_hi ? e_hi : r_hi);
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
           for (int t = 0; t < TM; ++t)
 #pragma unroll
@@ -645,11 +766,11 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
       }
     }
   }
-  if (cur_bin >= 0) flush_bin(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+  if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
 
   // ---- per-offset maxima: combine the two row halves, then one atomic per offset ----
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const float ov = __shfl_xor(best[j], 32, 64);
     const int ok = __shfl_xor(bestk[j], 32, 64);
     if (ov > best[j] || (ov == best[j] && ok >= 0 && (bestk[j] < 0 || ok < bestk[j]))) {
@@ -666,26 +787,65 @@ __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const SegDesc* __restric
   }
 }
 
-hipError_t launch_main(const SegDesc* segs_dev, const BankDev& b, const SearchDev& p,
-                       hipStream_t s) {
-  const size_t lds = main_lds_bytes(b.precision, b.L_pad);
-  const int64_t items = p.total_tiles * p.n_ranges;
-  if (b.precision == P_FP32) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_main<P_FP32>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_main<P_FP32>, dim3((unsigned)items), dim3(WG_THREADS), lds, s,
-                       segs_dev, b, p);
-  } else if (b.precision == P_BF16X3) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_main<P_BF16X3>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_main<P_BF16X3>, dim3((unsigned)items), dim3(WG_THREADS), lds, s,
-                       segs_dev, b, p);
-  } else {
-    return hipErrorInvalidValue;
+// Each work-group runs items blockIdx.x, blockIdx.x + gridDim.x, ...: one item per
+// work-group for a plain batch launch, a persistent loop for captured launches whose grid
+// is fixed while the batch changes.
+template <int PREC, int NB>
+__global__ __launch_bounds__(WG_THREADS, 1) void k_main(const BatchHdr* __restrict__ hdr,
+                                                        BankDev b, SearchDev p) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int64_t n_items = hdr->n_items;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    main_item<PREC, NB>(hdr, item, b, p, lds);
+    __syncthreads();   // the next item refills the strip
   }
+}
+
+template <int PREC, int NB>
+static hipError_t prepare_main_t(const BankDev& b) {
+  const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
+  return hipFuncSetAttribute((const void*)k_main<PREC, NB>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int PREC, int NB>
+static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                                const SearchDev& p, hipStream_t s) {
+  const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
+  hipLaunchKernelGGL((k_main<PREC, NB>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
+                     hdr, b, p);
   return hipGetLastError();
+}
+
+// Sets the kernel's dynamic-LDS limit; call before launching (and before capturing).
+hipError_t prepare_main(const BankDev& b, const SearchDev& p) {
+  if (b.precision == P_FP32) {
+    if (p.tn == 4) return prepare_main_t<P_FP32, 4>(b);
+    if (p.tn == 8) return prepare_main_t<P_FP32, 8>(b);
+  } else if (b.precision == P_BF16X3) {
+    if (p.tn == 4) return prepare_main_t<P_BF16X3, 4>(b);
+    if (p.tn == 8) return prepare_main_t<P_BF16X3, 8>(b);
+  } else if (b.precision == P_FP8) {
+    if (p.tn == 4) return prepare_main_t<P_FP8, 4>(b);
+    if (p.tn == 8) return prepare_main_t<P_FP8, 8>(b);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_main(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                       const SearchDev& p, hipStream_t s) {
+  if (blocks < 1) return hipSuccess;
+  if (b.precision == P_FP32) {
+    if (p.tn == 4) return launch_main_t<P_FP32, 4>(hdr, blocks, b, p, s);
+    if (p.tn == 8) return launch_main_t<P_FP32, 8>(hdr, blocks, b, p, s);
+  } else if (b.precision == P_BF16X3) {
+    if (p.tn == 4) return launch_main_t<P_BF16X3, 4>(hdr, blocks, b, p, s);
+    if (p.tn == 8) return launch_main_t<P_BF16X3, 8>(hdr, blocks, b, p, s);
+  } else if (b.precision == P_FP8) {
+    if (p.tn == 4) return launch_main_t<P_FP8, 4>(hdr, blocks, b, p, s);
+    if (p.tn == 8) return launch_main_t<P_FP8, 8>(hdr, blocks, b, p, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -693,9 +853,10 @@ hipError_t launch_main(const SegDesc* segs_dev, const BankDev& b, const SearchDe
 // m over non-degenerate windows (LDS-privatised), degenerate count, spectrum = fixed-point
 // sum / (2^40 W).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(const SegDesc* __restrict__ segs, BankDev b,
+__global__ __launch_bounds__(256) void k_finalize(const BatchHdr* __restrict__ hdr, BankDev b,
                                                   SearchDev p) {
-  const SegDesc& sg = segs[blockIdx.y];
+  if ((int)blockIdx.y >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
   __shared__ unsigned int hl[MAX_HIST_BINS];
   __shared__ unsigned int ndeg;
   const int tid = threadIdx.x;
@@ -736,23 +897,17 @@ __global__ __launch_bounds__(256) void k_finalize(const SegDesc* __restrict__ se
       sg.spectrum[i] = (double)sg.spec_acc[i] / SPEC_FIX_SCALE / (double)sg.W;
 }
 
-hipError_t launch_finalize(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W,
+hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
                            const BankDev& b, const SearchDev& p, hipStream_t s) {
-  int64_t blocks = (max_W + 1023) / 1024;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
-                     segs_dev, b, p);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)x_blocks, (unsigned)seg_slots), dim3(256), 0, s,
+                     hdr, b, p);
   return hipGetLastError();
 }
 
-hipError_t launch_norms(const SegDesc* segs_dev, int32_t n_segs, int64_t max_W, int L,
+hipError_t launch_norms(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks, int L,
                         int norm, hipStream_t s) {
-  int64_t blocks = (max_W + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_norms, dim3((unsigned)blocks, (unsigned)n_segs), dim3(256), 0, s,
-                     segs_dev, L, norm);
+  hipLaunchKernelGGL(k_norms, dim3((unsigned)x_blocks, (unsigned)seg_slots), dim3(256), 0, s,
+                     hdr, L, norm);
   return hipGetLastError();
 }
 

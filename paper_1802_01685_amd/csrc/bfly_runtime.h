@@ -1,0 +1,75 @@
+// Host-side runtime pieces shared by the search entry points (bfly_api.cpp) and the server
+// (bfly_server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include "bfly.h"
+#include "bfly_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+struct bf_bank {
+  bf_bank_desc desc;
+  bfly::GridDev grid;
+  bfly::BankDev dev;
+  int device;
+};
+
+namespace bfly {
+
+bf_status set_error(bf_status code, const char* fmt, ...);
+bf_status hip_error(hipError_t e, const char* what);
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Device buffers of one series: its samples, its workspace part, its outputs.
+struct SeriesBufs {
+  const float* x;
+  int64_t n;
+  double* pre;
+  int32_t* cnt;
+  double* inv_norm;
+  unsigned long long* mkey;
+  unsigned long long* spec_acc;
+  bf_result out;
+};
+
+// Bytes of one series' workspace part (prefix sums, counts, norms, maxima, spectrum sums).
+size_t series_ws_bytes(const BankDev& b, int64_t n);
+// Assigns the workspace pointers of a series whose workspace part starts at base.
+void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s);
+// Bytes of a batch table for n_segs series ([BatchHdr][SegDesc x n_segs], 256-aligned).
+inline size_t table_bytes(int32_t n_segs) {
+  return align256(sizeof(BatchHdr) + (size_t)n_segs * sizeof(SegDesc));
+}
+
+bf_status check_params(const bf_search_params* p);
+SearchDev make_search(const BankDev& b, const bf_search_params* p);
+bf_status device_slots(int* slots);
+int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots);
+
+// Fills a host batch table (hdr followed by the SegDescs) for the series s[0..n-1].
+struct TableInfo {
+  int64_t max_W = 0;
+  int64_t max_words = 0;
+  int64_t n_items = 0;
+};
+TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s, int32_t n,
+                     int slots, BatchHdr* hdr);
+
+// Per-kernel timing records (optional; see bf_set_timing).
+struct TimingSet {
+  hipEvent_t ev[6] = {};
+  int device = -1;
+};
+TimingSet* timing_slot(int device, bf_status* st);
+
+// Enqueues the five kernels of a search on `stream`, reading the batch table at table_dev.
+// prepare_main(b, sp) must have been called once before (outside any stream capture).
+bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr* table_dev,
+                          int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                          hipStream_t stream, TimingSet* te);
+
+}  // namespace bfly

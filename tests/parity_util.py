@@ -6,7 +6,7 @@ import numpy as np
 
 from oracle import bfly_oracle as O
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp8": 5e-2}
 
 
 def to_np(out: dict) -> dict:

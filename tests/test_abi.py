@@ -28,7 +28,9 @@ def test_header_declares_entry_points():
     syms = declared_symbols()
     for s in ("bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy",
               "bf_workspace_bytes", "bf_search_segment", "bf_search_batch", "bf_plan",
-              "bf_set_timing", "bf_kernel_times", "bf_last_error"):
+              "bf_set_timing", "bf_kernel_times", "bf_last_error", "bf_server_create",
+              "bf_server_request_bytes", "bf_submit", "bf_poll", "bf_fetch", "bf_cancel",
+              "bf_server_stats", "bf_server_destroy"):
         assert s in syms
 
 
@@ -46,6 +48,9 @@ def test_bank_bytes_and_validation_on_host(lib):
     assert lib.bank_bytes(d) == 65536 * 4096 * 4 + 256
     d3 = lib.make_desc(bank_params(3), "fp32")
     assert lib.bank_bytes(d3) == 720000 * 2016 * 4 + 256   # L_pad = 2016 (multiple of 32)
+    d8 = lib.make_desc(bank_params(2), "fp8")
+    # one byte per tap, then an int32 exponent per template, then the status word
+    assert lib.bank_bytes(d8) == 65536 * 4096 + 65536 * 4 + 256
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
         q = lib.make_desc(bank_params(2), "fp32")

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
 
 Tolerances (max relative error of the butterfly output m and of the spectrogram S over
-non-degenerate offsets): FP32 1e-5, BF16 hi/lo split 1e-4.  Argmax: the template the GPU
+non-degenerate offsets): FP32 1e-5, BF16 hi/lo split 1e-4, FP8 (e4m3 with power-of-two
+template and strip scales) 5e-2.  Argmax: the template the GPU
 reports must reach the FP64 maximum within 2*tol (so it must be the oracle's template
 wherever the FP64 top-2 margin exceeds 2*tol*m).  Histograms: exact against the floor-rule
 binning of the GPU's own maxima, and equal to the FP64 histogram except for maxima within
@@ -19,7 +20,7 @@ from synth import (BankParams, bank_params, cfg1_series, cfg2_series, cfg3_serie
 from tests.parity_util import TOL, check_against_oracle, check_hist, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-PRECS = ["fp32", "bf16x3"]
+PRECS = ["fp32", "bf16x3", "fp8"]
 
 
 @pytest.fixture(scope="module")

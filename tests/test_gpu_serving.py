@@ -1,0 +1,154 @@
+"""GPU tests of the serving loop: continuous batching through the C ABI.
+
+Each request's results must be identical, bit for bit, alone, in a mix of concurrent
+requests, and from a direct batched search; admission waits for the HBM budget; cancel,
+unknown tickets, over-budget requests and shutdown with pending work behave as declared.
+Every tick replays a captured graph, so the mix test also checks many graph replays against
+eager searches.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bfly_oracle as O  # noqa: E402
+from synth import BankParams, white_noise, chirp_samples  # noqa: E402
+from tests.parity_util import TOL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+P = BankParams(fs=1024.0, L=256, n_f0=24, n_fdot=20, f0_min=20.0, f0_max=400.0,
+               fdot_min=-300.0, fdot_max=300.0)
+
+
+@pytest.fixture(scope="module")
+def bf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_01685_amd import bfly
+    bfly.lib()
+    return bfly
+
+
+def _series(i, n):
+    x = white_noise(n, 900 + i)
+    if i % 3 == 0:
+        sig, _ = chirp_samples(n, P.fs, 0.3 * n / P.fs, 100.0 + 5 * i, 50.0 - 7 * i)
+        x = x + 0.4 * sig
+    return x.astype(np.float32)
+
+
+def _wait(bf, srv, tickets, timeout=120.0):
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            st = bf.poll(srv, t)[0]
+            if st in ("done", "failed", "cancelled"):
+                pending.discard(t)
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(pending)} requests still pending")
+        time.sleep(0.001)
+
+
+def _direct(bf, bank, x, prm):
+    out = bf.search_segment(bank, torch.from_numpy(x).cuda(), prm)
+    torch.cuda.synchronize()
+    r = {k: v.cpu().numpy() for k, v in out.items()}
+    r["hist"] = r["hist"].view(np.uint32)
+    return r
+
+
+def _same(a, b, label):
+    for k in ("max_abs", "argmax", "spec", "spectrum", "hist", "n_degenerate"):
+        assert np.array_equal(np.asarray(a[k]).view(np.uint8), np.asarray(b[k]).view(np.uint8)), \
+            (label, k)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_alone_equals_mix_equals_direct(bf, prec):
+    bank = bf.bank_create(P, prec)
+    prm = bf.make_params(t_block=4, hist_bins=64)
+    srv = bf.server_create(bank, hbm_budget_bytes=256 << 20, max_slots=8, ticks_in_flight=2,
+                           params=prm)
+    lengths = [1000 + 733 * i for i in range(20)]
+    xs = [_series(i, n) for i, n in enumerate(lengths)]
+    probe = 7
+    t = bf.submit(srv, xs[probe])
+    _wait(bf, srv, [t])
+    alone = bf.fetch(srv, t, lengths[probe])
+    tickets = [bf.submit(srv, x) for x in xs]          # arrive while others run
+    _wait(bf, srv, tickets)
+    stats = bf.server_stats(srv)
+    mix = [bf.fetch(srv, t, n) for t, n in zip(tickets, lengths)]
+    _same(alone, mix[probe], "alone vs mix")
+    for i in (0, 5, probe, 19):
+        _same(mix[i], _direct(bf, bank, xs[i], prm), f"mix vs direct {i}")
+    assert stats["ticks"] >= 3 and stats["done"] == 21
+    # and the served results are right
+    x64 = xs[probe].astype(np.float64)
+    orc = O.search(x64, P)
+    ok = ~orc["degen"]
+    rel = np.abs(mix[probe]["max_abs"][ok] - orc["m"][ok]) / orc["m"][ok]
+    assert rel.max() <= TOL[prec]
+    bf.server_destroy(srv)
+
+
+def test_budget_defers_admission(bf):
+    bank = bf.bank_create(P, "bf16x3")
+    prm = bf.make_params()
+    n = 30000
+    tmp = bf.server_create(bank, 64 << 20, params=prm)
+    per = bf.server_request_bytes(tmp, n)
+    bf.server_destroy(tmp)
+    srv = bf.server_create(bank, hbm_budget_bytes=2 * per + 4096, max_slots=16,
+                           ticks_in_flight=2, params=prm)
+    xs = [_series(i, n) for i in range(8)]
+    tickets = [bf.submit(srv, x) for x in xs]
+    seen_queued = bf.server_stats(srv)["queued"] > 0
+    _wait(bf, srv, tickets)
+    st = bf.server_stats(srv)
+    assert st["done"] == 8 and st["queued"] == 0 and st["on_device"] == 0
+    assert st["ticks"] >= 4          # at most two fit at a time
+    assert seen_queued
+    ref = _direct(bf, bank, xs[3], prm)
+    _same(bf.fetch(srv, tickets[3], n), ref, "budget")
+    bf.server_destroy(srv)
+
+
+def test_errors_cancel_and_shutdown(bf):
+    bank = bf.bank_create(P, "bf16x3")
+    prm = bf.make_params()
+    srv = bf.server_create(bank, hbm_budget_bytes=8 << 20, max_slots=2, ticks_in_flight=1,
+                           params=prm)
+    big = np.zeros(4_000_000, np.float32)
+    with pytest.raises(bf.BflyError) as e:
+        bf.submit(srv, big)
+    assert e.value.status == bf.BF_EBUDGET
+    with pytest.raises(bf.BflyError) as e:
+        bf.submit(srv, np.zeros(100, np.float32))       # shorter than L
+    assert e.value.status == bf.BF_EINVAL
+    with pytest.raises(bf.BflyError) as e:
+        bf.poll(srv, 123456)
+    assert e.value.status == bf.BF_ENOTFOUND
+    xs = [_series(i, 20000) for i in range(6)]
+    tickets = [bf.submit(srv, x) for x in xs]
+    bf.cancel(srv, tickets[-1])                        # still queued: dropped
+    _wait(bf, srv, tickets)
+    assert bf.poll(srv, tickets[-1])[0] == "cancelled"
+    with pytest.raises(bf.BflyError) as e:
+        bf.fetch(srv, tickets[-1], 20000)
+    assert e.value.status == bf.BF_ECANCELED
+    with pytest.raises(bf.BflyError) as e:
+        bf.fetch(srv, tickets[-1], 20000)              # forgotten after the fetch
+    assert e.value.status == bf.BF_ENOTFOUND
+    r0 = bf.fetch(srv, tickets[0], 20000)
+    assert r0["max_abs"].shape == (20000 - P.L + 1,)
+    # shutdown with work pending: queued requests are dropped, running ones drain
+    more = [bf.submit(srv, x) for x in xs]
+    assert len(more) == 6
+    t0 = time.time()
+    bf.server_destroy(srv)
+    assert time.time() - t0 < 60
