@@ -141,6 +141,9 @@ def main() -> int:
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--cpu-offsets", type=int, default=256, help="0 skips the oracle leg")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a known-size reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,6 +165,13 @@ def main() -> int:
     x = cfg2_series()
     xc = time_randomised(x, seed=102)
     xs = [torch.from_numpy(x).cuda(), torch.from_numpy(xc).cuda()]
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + written")
+        del src, dst
     torch.cuda.synchronize()
 
     log(f"timing {args.precision}: {args.warmup} warmup + {args.steps} steps")
