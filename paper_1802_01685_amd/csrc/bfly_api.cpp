@@ -185,16 +185,18 @@ void release_staging(Staging* s, bool recorded) {
 
 int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
-// Offset blocks of 32 per wave of the contraction kernel.  BF_TN=4|8 overrides the default
-// (a tuning knob for experiments).
-int32_t choose_tn(int precision) {
-  static int forced = -1;
-  if (forced < 0) {
-    const char* e = getenv("BF_TN");
-    forced = (e && (atoi(e) == 4 || atoi(e) == 8)) ? atoi(e) : 0;
+// Tile shape of the contraction kernel: tm template blocks x tn offset blocks (of 32) per
+// wave.  BF_TILE=<tm>x<tn> (e.g. "2x8") overrides the default -- a tuning knob for
+// experiments; the results do not depend on it except through FP8's per-strip scales.
+void choose_tile(int precision, int32_t* tm, int32_t* tn) {
+  *tm = 2;
+  *tn = 4;
+  const char* e = getenv("BF_TILE");
+  int a = 0, c = 0;
+  if (e && sscanf(e, "%dx%d", &a, &c) == 2 && main_variant_exists(precision, a, c)) {
+    *tm = a;
+    *tn = c;
   }
-  if (forced) return forced;
-  return precision == BF_FP32 ? 4 : 4;
 }
 
 // Per-thread pool of timing records, collected by bf_kernel_times.  The events live until
@@ -329,7 +331,7 @@ SearchDev make_search(const BankDev& b, const bf_search_params* prm) {
   sp.hist_bins = prm->hist_bins;
   sp.hist_lo = prm->hist_lo;
   sp.hist_hi = prm->hist_hi;
-  sp.tn = choose_tn(b.precision);
+  choose_tile(b.precision, &sp.tm, &sp.tn);
   sp.n_wg = 32 * sp.tn * WG_WAVES;
   return sp;
 }
@@ -350,18 +352,21 @@ bf_status device_slots(int* slots) {
 
 // Splits the bank sweep into bin ranges so that the work items fill the device in whole
 // waves: estimated makespan = ceil(items / slots) * (tiles of the largest range), plus a
-// small per-item cost (strip fill and flushes).
-int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots) {
+// small per-item cost (strip fill and flushes).  With at least 8 bins the count is a
+// multiple of 8, so that each XCD sweeps its own ranges (see the item order in k_main).
+constexpr int XCDS = 8;
+int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots, int tm) {
   double best_cost = 1e300;
   int32_t best_r = 1;
   const int32_t rmax = std::min<int32_t>(b.n_bins, 4096);
-  for (int32_t r = 1; r <= rmax; ++r) {
+  const int32_t step = b.n_bins >= XCDS ? XCDS : 1;
+  for (int32_t r = step; r <= rmax; r += step) {
     const int64_t items = total_tiles * r;
     if (items > (int64_t)0x7FFFFFFF) break;
     // the largest range (ranges differ by at most one bin)
     const int32_t bins = (b.n_bins + r - 1) / r;
     const int64_t k_span = (int64_t)bins * b.n_fdot;
-    const int64_t max_tiles = (k_span + TILE_K - 1) / TILE_K + 1;
+    const int64_t max_tiles = (k_span + 32 * tm - 1) / (32 * tm) + 1;
     const int64_t waves = (items + slots - 1) / slots;
     const double cost = (double)waves * (double)max_tiles + 0.02 * (double)waves;
     if (cost < best_cost * 0.999) {
@@ -404,7 +409,7 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
   std::memset(hdr, 0, sizeof(BatchHdr));
   hdr->n_segs = n;
   hdr->total_tiles = tiles;
-  hdr->n_ranges = plan_ranges(b, tiles, slots);
+  hdr->n_ranges = plan_ranges(b, tiles, slots, sp.tm);
   hdr->n_items = tiles * hdr->n_ranges;
   ti.n_items = hdr->n_items;
   return ti;
@@ -614,13 +619,17 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   int64_t tiles = 0;
   for (int32_t i = 0; i < n_segs; ++i) {
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
-    const int64_t n_wg = 32 * (int64_t)choose_tn(bank->dev.precision) * WG_WAVES;
+    int32_t tm = 2, tn = 4;
+    choose_tile(bank->dev.precision, &tm, &tn);
+    const int64_t n_wg = 32 * (int64_t)tn * WG_WAVES;
     tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
   }
   int slots = 0;
   bf_status st = device_slots(&slots);
   if (st != BF_OK) return st;
-  const int32_t r = plan_ranges(bank->dev, tiles, slots);
+  int32_t tm = 2, tn = 4;
+  choose_tile(bank->dev.precision, &tm, &tn);
+  const int32_t r = plan_ranges(bank->dev, tiles, slots, tm);
   if (n_ranges) *n_ranges = r;
   if (n_items) *n_items = tiles * r;
   return BF_OK;

@@ -9,13 +9,12 @@ namespace bfly {
 
 // ---- tile geometry of the contraction kernel -------------------------------------------
 // A work-group of 4 waves owns 4 * 32 * tn consecutive offsets; each wave owns tn blocks
-// of 32 offsets (tn = 4 or 8, chosen per search).  All four waves sweep the same
-// templates, TM blocks of 32 per step, and the taps in chunks of KCH.
+// of 32 offsets.  All four waves sweep the same templates, tm blocks of 32 per step, and
+// the taps in chunks of KCH.  (tm, tn) is a compiled tile shape chosen per search.
 constexpr int WAVE = 64;
 constexpr int WG_WAVES = 4;
 constexpr int WG_THREADS = WAVE * WG_WAVES;
-constexpr int TM = 2;                         // 32-template blocks per template tile
-constexpr int TILE_K = 32 * TM;               // templates per template tile
+constexpr int TILE_K = 64;                    // K_pad granule (largest template tile)
 constexpr int MAX_N_WG = 32 * 8 * WG_WAVES;  // offsets per work item at tn = 8
 constexpr int KCH = 16;                       // taps per chunk, FP32 and BF16 forms
 constexpr int KCH_FP8 = 64;                   // taps per chunk, FP8 form
@@ -91,6 +90,7 @@ struct SearchDev {
   int32_t norm;
   int32_t t_block;
   int32_t hist_bins;
+  int32_t tm;           // 32-template blocks per template tile (1 or 2)
   int32_t tn;           // 32-offset blocks per wave (4 or 8)
   int32_t n_wg;         // offsets per work item = 4 * 32 * tn
   double hist_lo, hist_hi;
@@ -119,6 +119,7 @@ hipError_t launch_prefix(const BatchHdr* hdr, int32_t seg_slots, hipStream_t s);
 hipError_t launch_norms(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks, int L,
                         int norm, hipStream_t s);
 hipError_t prepare_main(const BankDev& b, const SearchDev& p);
+bool main_variant_exists(int precision, int tm, int tn);
 hipError_t launch_main(const BatchHdr* hdr, int64_t main_blocks, const BankDev& b,
                        const SearchDev& p, hipStream_t s);
 hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,

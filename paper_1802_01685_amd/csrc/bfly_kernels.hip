@@ -330,11 +330,11 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 // The contraction with the fused reductions.
 //
 // Work item = (series, offset tile of n_wg = 128*NB offsets, bin range).  Items are numbered
-// range-major, so the work-groups resident at any time sweep the same templates and share
-// them through L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + n_wg + L_pad) (zero
+// range-fastest and the planner uses a multiple of 8 ranges, so each XCD's work-groups sweep
+// only their own part of the bank, in step, and share it through that XCD's L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + n_wg + L_pad) (zero
 // past the end; non-finite samples as 0 -- their windows are degenerate and discarded),
 // then each wave sweeps the item's template tiles: for each tile, a full K-loop over the
-// taps into TM x NB accumulators of 32 x 32, then the epilogue.
+// taps into MB x NB accumulators of 32 x 32, then the epilogue.
 //
 // MFMA fragments (64 lanes, lane = h*32 + n):
 //   FP32  v_mfma_f32_32x32x2_f32: A lane holds h_k[kk + h] of template row n,
@@ -356,28 +356,28 @@ struct ItemCtx {
   int64_t k_lo, k_hi;  // local template range owned by the item (whole bins)
 };
 
-template <int PREC>
+template <int PREC, int MB>
 struct AFrag;
-template <>
-struct AFrag<P_FP32> {
-  float4 v[TM][2];    // 8 taps per lane per block per chunk
+template <int MB>
+struct AFrag<P_FP32, MB> {
+  float4 v[MB][2];    // 8 taps per lane per block per chunk
 };
-template <>
-struct AFrag<P_BF16X3> {
-  uint4 v[TM][2];     // [block][plane hi/lo]
+template <int MB>
+struct AFrag<P_BF16X3, MB> {
+  uint4 v[MB][2];     // [block][plane hi/lo]
 };
-template <>
-struct AFrag<P_FP8> {
-  uint4 v[TM][2];     // 32 e4m3 codes per lane per block per chunk
+template <int MB>
+struct AFrag<P_FP8, MB> {
+  uint4 v[MB][2];     // 32 e4m3 codes per lane per block per chunk
 };
 
-template <int PREC>
-__device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t blk0, int c,
+template <int PREC, int MB>
+__device__ __forceinline__ void load_a(AFrag<PREC, MB>& f, const void* bank, int64_t blk0, int c,
                                        int nchunks, int lane) {
   if constexpr (PREC == P_FP32) {
     const float4* A = (const float4*)bank;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
+    for (int t = 0; t < MB; ++t) {
       const int64_t idx = (((blk0 + t) * nchunks + c) * 64 + lane) * 2;
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 1];
@@ -385,7 +385,7 @@ __device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t
   } else if constexpr (PREC == P_BF16X3) {
     const uint4* A = (const uint4*)bank;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
+    for (int t = 0; t < MB; ++t) {
       const int64_t idx = (((blk0 + t) * nchunks + c) * 2) * 64 + lane;
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 64];
@@ -393,7 +393,7 @@ __device__ __forceinline__ void load_a(AFrag<PREC>& f, const void* bank, int64_t
   } else {
     const uint4* A = (const uint4*)bank;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
+    for (int t = 0; t < MB; ++t) {
       const int64_t idx = (((blk0 + t) * nchunks + c) * 64 + lane) * 2;
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 1];
@@ -421,7 +421,8 @@ struct BFrag<P_FP8, NB> {
   uint4 v[NB][2];     // [offset block][32 codes]
 };
 
-template <int PREC, int NB>
+// Strip fragments of chunk c for the offset blocks j in [J0, J1) (all by default).
+template <int PREC, int NB, int J0 = 0, int J1 = NB>
 __device__ __forceinline__ void load_b(BFrag<PREC, NB>& f, const char* lds, int off_w, int c,
                                        int n, int h, int plane_bytes) {
   if constexpr (PREC == P_FP32) {
@@ -430,14 +431,16 @@ __device__ __forceinline__ void load_b(BFrag<PREC, NB>& f, const char* lds, int 
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) f.v[s][j] = sx[p0 + 32 * j + 2 * s];
+      for (int j = J0; j < J1; ++j) f.v[s][j] = sx[p0 + 32 * j + 2 * s];
   } else if constexpr (PREC == P_FP8) {
     // 8 copies shifted by 0..7 samples, interleaved per 8-sample cell (8 bytes each):
-    // a lane's 32 consecutive codes are four 8-byte-aligned reads.
+    // a lane's 32 consecutive codes are four 8-byte-aligned reads.  Block j and chunk c
+    // move the cell by 4j and 8c, i.e. the address by 256j + 512c bytes.
+    const int p0 = off_w + n + 32 * h;
+    const int base = (p0 >> 3) * 64 + (p0 & 7) * 8 + 512 * c;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int p = off_w + 32 * j + n + 64 * c + 32 * h;
-      const int addr = (p >> 3) * 64 + (p & 7) * 8;
+    for (int j = J0; j < J1; ++j) {
+      const int addr = base + 256 * j;
       const uint2 u0 = *(const uint2*)(lds + addr);
       const uint2 u1 = *(const uint2*)(lds + addr + 64);
       const uint2 u2 = *(const uint2*)(lds + addr + 128);
@@ -446,10 +449,12 @@ __device__ __forceinline__ void load_b(BFrag<PREC, NB>& f, const char* lds, int 
       f.v[j][1] = make_uint4(u2.x, u2.y, u3.x, u3.y);
     }
   } else {
+    // Block j and chunk c move the 4-sample cell by 8j and 4c: the address by 256j + 128c.
+    const int p0 = off_w + n + 8 * h;
+    const int base = (p0 >> 2) * 32 + (p0 & 3) * 8 + 128 * c;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int p = off_w + 32 * j + n + 16 * c + 8 * h;
-      const int addr = (p >> 2) * 32 + (p & 3) * 8;
+    for (int j = J0; j < J1; ++j) {
+      const int addr = base + 256 * j;
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
         const uint2 u0 = *(const uint2*)(lds + pl * plane_bytes + addr);
@@ -465,18 +470,19 @@ struct U8 {
   uint4 a, b;
 };
 
-template <int PREC, int NB>
-__device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][NB], const AFrag<PREC>& a,
-                                          const BFrag<PREC, NB>& bf, const int (&sa)[TM],
+// MFMAs of one chunk for the offset blocks j in [J0, J1) (all of them by default).
+template <int PREC, int MB, int NB, int J0 = 0, int J1 = NB>
+__device__ __forceinline__ void mma_chunk(f32x16 (&acc)[MB][NB], const AFrag<PREC, MB>& a,
+                                          const BFrag<PREC, NB>& bf, const int (&sa)[MB],
                                           int sb) {
   if constexpr (PREC == P_FP8) {
     // e4m3 x e4m3, with the E8M0 scales 2^-e_k (per template row, per lane) and 2^-e_x
     // (per strip) undoing the power-of-two scaling of both operands.
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
+    for (int t = 0; t < MB; ++t) {
       const i32x8 av = __builtin_bit_cast(i32x8, (U8{a.v[t][0], a.v[t][1]}));
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
+      for (int j = J0; j < J1; ++j) {
         const i32x8 bv = __builtin_bit_cast(i32x8, (U8{bf.v[j][0], bf.v[j][1]}));
         acc[t][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[t][j], 0, 0, 0,
                                                                     sa[t], 0, sb);
@@ -486,10 +492,10 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][NB], const AFrag<PRE
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int t = 0; t < TM; ++t) {
+      for (int t = 0; t < MB; ++t) {
         const float av = f4get(a.v[t][s >> 2], s & 3);
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = J0; j < J1; ++j)
           acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf.v[s][j], acc[t][j], 0, 0, 0);
       }
   } else {
@@ -498,10 +504,10 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[TM][NB], const AFrag<PRE
     for (int term = 0; term < 3; ++term) {
       const int pa = term == 2 ? 1 : 0, pb = term == 1 ? 1 : 0;
 #pragma unroll
-      for (int t = 0; t < TM; ++t) {
+      for (int t = 0; t < MB; ++t) {
         const bf16x8 av = __builtin_bit_cast(bf16x8, a.v[t][pa]);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
+        for (int j = J0; j < J1; ++j) {
           const bf16x8 b = __builtin_bit_cast(bf16x8, bf.v[j][pb]);
           acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b, acc[t][j], 0, 0, 0);
         }
@@ -541,7 +547,7 @@ __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
 }
 
 // One work item: strip fill, template sweep, flushes.
-template <int PREC, int NB>
+template <int PREC, int MB, int NB>
 __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int64_t item,
                                           const BankDev& b, const SearchDev& p, char* lds) {
   const SegDesc* segs = hdr_segs(hdr);
@@ -551,8 +557,10 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int n_ranges = hdr->n_ranges;
 
   // ---- which item ----
-  const int r = (int)(item / total_tiles);
-  const int64_t tt = item % total_tiles;
+  // Bin range fastest: work-group i runs on XCD i mod 8, so with a multiple of 8 ranges
+  // each XCD only ever sweeps its own ranges and the bank streams into each L2 once.
+  const int r = (int)(item % n_ranges);
+  const int64_t tt = item / n_ranges;
   int lo = 0, hi = hdr->n_segs - 1;
   while (lo < hi) {  // last series with tile0 <= tt
     const int mid = (lo + hi + 1) >> 1;
@@ -564,8 +572,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int b_hi = (int)((int64_t)(r + 1) * b.n_bins / n_ranges);
   const int64_t k_lo = (int64_t)b_lo * b.n_fdot;
   const int64_t k_hi = (int64_t)b_hi * b.n_fdot;
-  const int64_t tile_lo = k_lo / TILE_K;
-  const int64_t tile_hi = (k_hi + TILE_K - 1) / TILE_K;
+  const int64_t tile_lo = k_lo / (32 * MB);
+  const int64_t tile_hi = (k_hi + (32 * MB) - 1) / (32 * MB);
 
   // ---- strip fill ----
   const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
@@ -656,52 +664,88 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int nfd = b.n_fdot;
 
   for (int64_t kt = tile_lo; kt < tile_hi; ++kt) {
-    f32x16 acc[TM][NB];
+    f32x16 acc[MB][NB];
 #pragma unroll
-    for (int t = 0; t < TM; ++t)
+    for (int t = 0; t < MB; ++t)
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[t][j] = (f32x16){};
 
-    const int64_t blk0 = kt * TM;
-    int sa[TM];
+    const int64_t blk0 = kt * MB;
+    int sa[MB];
 #pragma unroll
-    for (int t = 0; t < TM; ++t)
+    for (int t = 0; t < MB; ++t)
       sa[t] = PREC == P_FP8 ? 127 - b.texp[(blk0 + t) * 32 + n] : 127;
     // Software pipeline over chunk pairs (n_chunks is even): while the MFMAs of chunk c
     // run, the template fragments of chunk c+1 and the strip fragments of chunk c+1 are in
     // flight.  Scheduling barriers keep the compiler from sinking the loads next to their
     // uses.  The prefetches past the last chunk re-read a valid chunk and are unused.
     const int nc = b.n_chunks;
-    AFrag<PREC> a0, a1;
-    BFrag<PREC, NB> b0, b1;
+    AFrag<PREC, MB> a0, a1;
     __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
     __builtin_amdgcn_sched_barrier(0);
-    load_a<PREC>(a0, b.data, blk0, 0, nc, lane);
-    __builtin_amdgcn_sched_barrier(0);
-    load_b<PREC, NB>(b0, lds, off_w, 0, n, h, plane_bytes);
-    __builtin_amdgcn_sched_barrier(0);
-    for (int c = 0; c < nc; c += 2) {
-      load_a<PREC>(a1, b.data, blk0, c + 1, nc, lane);
+    if constexpr (NB <= 4) {
+      // Two strip-fragment buffers: chunk c+1's fragments load while chunk c's MFMAs run.
+      BFrag<PREC, NB> b0, b1;
+      load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
-      load_b<PREC, NB>(b1, lds, off_w, c + 1, n, h, plane_bytes);
+      load_b<PREC, NB>(b0, lds, off_w, 0, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
-      mma_chunk<PREC, NB>(acc, a0, b0, sa, sb);
+      for (int c = 0; c < nc; c += 2) {
+        load_a<PREC, MB>(a1, b.data, blk0, c + 1, nc, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB>(b1, lds, off_w, c + 1, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB>(acc, a0, b0, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        const int c2 = c + 2 < nc ? c + 2 : nc - 1;
+        load_a<PREC, MB>(a0, b.data, blk0, c2, nc, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB>(b0, lds, off_w, c2, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB>(acc, a1, b1, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      // One strip-fragment buffer in two halves: as soon as the MFMAs of one half of the
+      // offset blocks are issued, that half reloads for the next chunk, while the other
+      // half's MFMAs run.
+      constexpr int H = NB / 2;
+      BFrag<PREC, NB> bb;
+      load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
-      const int c2 = c + 2 < nc ? c + 2 : nc - 1;
-      load_a<PREC>(a0, b.data, blk0, c2, nc, lane);
+      load_b<PREC, NB, 0, NB>(bb, lds, off_w, 0, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
-      load_b<PREC, NB>(b0, lds, off_w, c2, n, h, plane_bytes);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_chunk<PREC, NB>(acc, a1, b1, sa, sb);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int c = 0; c < nc; c += 2) {
+        load_a<PREC, MB>(a1, b.data, blk0, c + 1, nc, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB, 0, H>(acc, a0, bb, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB, 0, H>(bb, lds, off_w, c + 1, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB, H, NB>(acc, a0, bb, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB, H, NB>(bb, lds, off_w, c + 1, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+        const int c2 = c + 2 < nc ? c + 2 : nc - 1;
+        load_a<PREC, MB>(a0, b.data, blk0, c2, nc, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB, 0, H>(acc, a1, bb, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB, 0, H>(bb, lds, off_w, c2, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk<PREC, MB, NB, H, NB>(acc, a1, bb, sa, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b<PREC, NB, H, NB>(bb, lds, off_w, c2, n, h, plane_bytes);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
 
     // ---- epilogue: lane rows are 32t + 8g + 4h + i4 of the tile ----
-    const int64_t kbase = kt * TILE_K;
+    const int64_t kbase = kt * (32 * MB);
     const int r_lo = (int)((k_lo > kbase ? k_lo : kbase) - kbase);        // rows owned
-    const int r_hi = (int)((k_hi < kbase + TILE_K ? k_hi : kbase + TILE_K) - kbase);
+    const int r_hi = (int)((k_hi < kbase + (32 * MB) ? k_hi : kbase + (32 * MB)) - kbase);
     const int bA = (int)((kbase + r_lo) / nfd), bB = (int)((kbase + r_hi - 1) / nfd);
-    if (r_lo == 0 && r_hi == TILE_K && bA == bB) {
+    if (r_lo == 0 && r_hi == (32 * MB) && bA == bB) {
       // whole tile owned and inside one bin
       if (bA != cur_bin) {
         if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
@@ -715,12 +759,12 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       for (int j = 0; j < NB; ++j) {
         float mx = 0.0f;
 #pragma unroll
-        for (int t = 0; t < TM; ++t)
+        for (int t = 0; t < MB; ++t)
 #pragma unroll
           for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fabsf(acc[t][j][v]));
         int row = 0;
 #pragma unroll
-        for (int t = TM - 1; t >= 0; --t)
+        for (int t = MB - 1; t >= 0; --t)
 #pragma unroll
           for (int v = 15; v >= 0; --v)
             row = fabsf(acc[t][j][v]) == mx ? 32 * t + 8 * (v >> 2) + 4 * h + (v & 3) : row;
@@ -734,7 +778,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int t = 0; t < TM; ++t)
+        for (int t = 0; t < MB; ++t)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -756,7 +800,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 #pragma unroll
         for (int j = 0; j < NB; ++j)
 #pragma unroll
-          for (int t = 0; t < TM; ++t)
+          for (int t = 0; t < MB; ++t)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
               const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -790,62 +834,66 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 // Each work-group runs items blockIdx.x, blockIdx.x + gridDim.x, ...: one item per
 // work-group for a plain batch launch, a persistent loop for captured launches whose grid
 // is fixed while the batch changes.
-template <int PREC, int NB>
+template <int PREC, int MB, int NB>
 __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const BatchHdr* __restrict__ hdr,
                                                         BankDev b, SearchDev p) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int64_t n_items = hdr->n_items;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    main_item<PREC, NB>(hdr, item, b, p, lds);
+    main_item<PREC, MB, NB>(hdr, item, b, p, lds);
     __syncthreads();   // the next item refills the strip
   }
 }
 
-template <int PREC, int NB>
+template <int PREC, int MB, int NB>
 static hipError_t prepare_main_t(const BankDev& b) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  return hipFuncSetAttribute((const void*)k_main<PREC, NB>,
+  return hipFuncSetAttribute((const void*)k_main<PREC, MB, NB>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int PREC, int NB>
+template <int PREC, int MB, int NB>
 static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                 const SearchDev& p, hipStream_t s) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  hipLaunchKernelGGL((k_main<PREC, NB>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
+  hipLaunchKernelGGL((k_main<PREC, MB, NB>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
                      hdr, b, p);
   return hipGetLastError();
 }
 
+// The compiled tile shapes (template blocks x offset blocks per wave), per precision.
+#define BFLY_DISPATCH(FN, ...)                                                         \
+  do {                                                                                 \
+    const int v_ = p.tm * 16 + p.tn;                                                   \
+    if (b.precision == P_FP32) {                                                       \
+      if (v_ == 2 * 16 + 4) return FN<P_FP32, 2, 4>(__VA_ARGS__);                      \
+      if (v_ == 1 * 16 + 8) return FN<P_FP32, 1, 8>(__VA_ARGS__);                      \
+    } else if (b.precision == P_BF16X3) {                                              \
+      if (v_ == 2 * 16 + 4) return FN<P_BF16X3, 2, 4>(__VA_ARGS__);                    \
+      if (v_ == 1 * 16 + 8) return FN<P_BF16X3, 1, 8>(__VA_ARGS__);                    \
+      if (v_ == 2 * 16 + 8) return FN<P_BF16X3, 2, 8>(__VA_ARGS__);                    \
+    } else if (b.precision == P_FP8) {                                                 \
+      if (v_ == 2 * 16 + 4) return FN<P_FP8, 2, 4>(__VA_ARGS__);                       \
+      if (v_ == 1 * 16 + 8) return FN<P_FP8, 1, 8>(__VA_ARGS__);                       \
+    }                                                                                  \
+    return hipErrorInvalidValue;                                                       \
+  } while (0)
+
+bool main_variant_exists(int precision, int tm, int tn) {
+  const int v = tm * 16 + tn;
+  if (precision == P_BF16X3) return v == 36 || v == 24 || v == 40;
+  return v == 36 || v == 24;
+}
+
 // Sets the kernel's dynamic-LDS limit; call before launching (and before capturing).
 hipError_t prepare_main(const BankDev& b, const SearchDev& p) {
-  if (b.precision == P_FP32) {
-    if (p.tn == 4) return prepare_main_t<P_FP32, 4>(b);
-    if (p.tn == 8) return prepare_main_t<P_FP32, 8>(b);
-  } else if (b.precision == P_BF16X3) {
-    if (p.tn == 4) return prepare_main_t<P_BF16X3, 4>(b);
-    if (p.tn == 8) return prepare_main_t<P_BF16X3, 8>(b);
-  } else if (b.precision == P_FP8) {
-    if (p.tn == 4) return prepare_main_t<P_FP8, 4>(b);
-    if (p.tn == 8) return prepare_main_t<P_FP8, 8>(b);
-  }
-  return hipErrorInvalidValue;
+  BFLY_DISPATCH(prepare_main_t, b);
 }
 
 hipError_t launch_main(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                        const SearchDev& p, hipStream_t s) {
   if (blocks < 1) return hipSuccess;
-  if (b.precision == P_FP32) {
-    if (p.tn == 4) return launch_main_t<P_FP32, 4>(hdr, blocks, b, p, s);
-    if (p.tn == 8) return launch_main_t<P_FP32, 8>(hdr, blocks, b, p, s);
-  } else if (b.precision == P_BF16X3) {
-    if (p.tn == 4) return launch_main_t<P_BF16X3, 4>(hdr, blocks, b, p, s);
-    if (p.tn == 8) return launch_main_t<P_BF16X3, 8>(hdr, blocks, b, p, s);
-  } else if (b.precision == P_FP8) {
-    if (p.tn == 4) return launch_main_t<P_FP8, 4>(hdr, blocks, b, p, s);
-    if (p.tn == 8) return launch_main_t<P_FP8, 8>(hdr, blocks, b, p, s);
-  }
-  return hipErrorInvalidValue;
+  BFLY_DISPATCH(launch_main_t, hdr, blocks, b, p, s);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -48,7 +48,7 @@ inline size_t table_bytes(int32_t n_segs) {
 bf_status check_params(const bf_search_params* p);
 SearchDev make_search(const BankDev& b, const bf_search_params* p);
 bf_status device_slots(int* slots);
-int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots);
+int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots, int tm);
 
 // Fills a host batch table (hdr followed by the SegDescs) for the series s[0..n-1].
 struct TableInfo {
