@@ -61,7 +61,10 @@ typedef enum {
 typedef enum {
   BF_FP32 = 0,   /* float32 templates and data, float32 MFMA */
   BF_BF16X3 = 1, /* bf16 hi+lo split of templates and data; hi*hi + hi*lo + lo*hi */
-  BF_FP8 = 2     /* e4m3 templates with a per-template power-of-two scale (reserved) */
+  BF_FP8 = 2,    /* OCP e4m3 templates and data with power-of-two scales (per template, per
+                    strip), undone by the MFMA scale operands; ~10% worst-case error */
+  BF_F16X2 = 3   /* fp16 hi+lo split of the templates, fp16 data with a power-of-two strip
+                    scale; h_hi*x + h_lo*x (two MFMA products per tap) */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;
@@ -118,7 +121,8 @@ typedef struct {
 /* Outputs of one series (device pointers, caller-owned; NULL = not requested).
  *   max_abs[W]      butterfly output m (float32)
  *   argmax[W]       global template index reaching m; -1 on degenerate windows
- *   spec[R][B]      spectrogram, R = ceil(W / t_block) rows, B = n_bins, float32
+ *   spec[B][R]      spectrogram, bin-major: row i holds f0 bin i over R = ceil(W / t_block)
+ *                   time blocks (max over each block of t_block offsets), float32
  *   spectrum[B]     (1/W) sum_tau S(tau, i) over the undecimated spectrogram (float64)
  *   hist[hist_bins] histogram of m over non-degenerate windows (uint32)
  *   n_degenerate[1] number of degenerate windows (int64) */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbfly.so")
 
 BF_OK, BF_EINVAL, BF_ENOMEM, BF_EBUDGET, BF_EAGAIN, BF_ENOTFOUND, BF_EHIP, BF_ECANCELED = (
     0, -1, -2, -3, -4, -5, -6, -7)
-PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp8": 2}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp8": 2, "f16x2": 3}
 NORMS = {"centred": 0, "raw": 1}
 STATUS_NAMES = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ENOMEM", -3: "BF_EBUDGET",
                 -4: "BF_EAGAIN", -5: "BF_ENOTFOUND", -6: "BF_EHIP", -7: "BF_ECANCELED"}
@@ -222,7 +222,7 @@ def alloc_outputs(bank: Bank, n: int, params: SearchParams, device,
     W = n - bank.desc.L + 1
     rows = -(-W // params.t_block)
     shapes = {"max_abs": ((W,), torch.float32), "argmax": ((W,), torch.int32),
-              "spec": ((rows, bank.n_bins), torch.float32),
+              "spec": ((bank.n_bins, rows), torch.float32),      # bin-major
               "spectrum": ((bank.n_bins,), torch.float64),
               "hist": ((params.hist_bins,), torch.int32),  # uint32 bit pattern
               "n_degenerate": ((1,), torch.int64)}
@@ -346,7 +346,7 @@ def fetch(server: Server, ticket: int, n: int) -> dict:
     W = n - server.bank.desc.L + 1
     rows = -(-W // server.params.t_block)
     out = {"max_abs": np.empty(W, np.float32), "argmax": np.empty(W, np.int32),
-           "spec": np.empty((rows, server.bank.n_bins), np.float32),
+           "spec": np.empty((server.bank.n_bins, rows), np.float32),
            "spectrum": np.empty(server.bank.n_bins, np.float64),
            "hist": np.empty(server.params.hist_bins, np.uint32),
            "n_degenerate": np.empty(1, np.int64)}

@@ -66,7 +66,8 @@ bf_status check_desc(const bf_bank_desc* d) {
   if (d->shard_count < 1 || d->shard_index < 0 || d->shard_index >= d->shard_count ||
       d->shard_count > d->n_f0)
     return fail(BF_EINVAL, "need 0 <= shard_index < shard_count <= n_f0");
-  if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8)
+  if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8 &&
+      d->precision != BF_F16X2)
     return fail(BF_EINVAL, "precision %d is not available", d->precision);
   const double v[4] = {d->f0_min, d->f0_max, d->fdot_min, d->fdot_max};
   for (double x : v)
@@ -186,16 +187,23 @@ void release_staging(Staging* s, bool recorded) {
 int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
 // Tile shape of the contraction kernel: tm template blocks x tn offset blocks (of 32) per
-// wave.  BF_TILE=<tm>x<tn> (e.g. "2x8") overrides the default -- a tuning knob for
-// experiments; the results do not depend on it except through FP8's per-strip scales.
-void choose_tile(int precision, int32_t* tm, int32_t* tn) {
+// wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i] (e.g. "2x8i", i = interleaved)
+// overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
+// depend on it (FP8 does, through its per-strip scales).
+void choose_tile(int precision, int32_t* tm, int32_t* tn, int32_t* pipe) {
   *tm = 2;
   *tn = 4;
+  *pipe = 0;
   const char* e = getenv("BF_TILE");
   int a = 0, c = 0;
-  if (e && sscanf(e, "%dx%d", &a, &c) == 2 && main_variant_exists(precision, a, c)) {
-    *tm = a;
-    *tn = c;
+  char il = 0;
+  if (e && sscanf(e, "%dx%d%c", &a, &c, &il) >= 2) {
+    const int pp = il == 'i' ? 1 : 0;
+    if (main_variant_exists(precision, a, c, pp)) {
+      *tm = a;
+      *tn = c;
+      *pipe = pp;
+    }
   }
 }
 
@@ -331,7 +339,7 @@ SearchDev make_search(const BankDev& b, const bf_search_params* prm) {
   sp.hist_bins = prm->hist_bins;
   sp.hist_lo = prm->hist_lo;
   sp.hist_hi = prm->hist_hi;
-  choose_tile(b.precision, &sp.tm, &sp.tn);
+  choose_tile(b.precision, &sp.tm, &sp.tn, &sp.pipe);
   sp.n_wg = 32 * sp.tn * WG_WAVES;
   return sp;
 }
@@ -619,16 +627,16 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   int64_t tiles = 0;
   for (int32_t i = 0; i < n_segs; ++i) {
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
-    int32_t tm = 2, tn = 4;
-    choose_tile(bank->dev.precision, &tm, &tn);
+    int32_t tm = 2, tn = 4, pp = 0;
+    choose_tile(bank->dev.precision, &tm, &tn, &pp);
     const int64_t n_wg = 32 * (int64_t)tn * WG_WAVES;
     tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
   }
   int slots = 0;
   bf_status st = device_slots(&slots);
   if (st != BF_OK) return st;
-  int32_t tm = 2, tn = 4;
-  choose_tile(bank->dev.precision, &tm, &tn);
+  int32_t tm = 2, tn = 4, pp = 0;
+  choose_tile(bank->dev.precision, &tm, &tn, &pp);
   const int32_t r = plan_ranges(bank->dev, tiles, slots, tm);
   if (n_ranges) *n_ranges = r;
   if (n_items) *n_items = tiles * r;

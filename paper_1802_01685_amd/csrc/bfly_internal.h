@@ -23,7 +23,10 @@ constexpr int MAX_L = 8192;
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
 
-enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2 };
+enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3 };
+
+// F16X2: templates are stored as fp16 hi + lo of h * 2^F16_TEMPLATE_EXP.
+constexpr int F16_TEMPLATE_EXP = 10;
 
 // Taps per K-loop chunk; L_pad is a multiple of twice this.
 constexpr int chunk_taps(int precision) { return precision == P_FP8 ? KCH_FP8 : KCH; }
@@ -92,6 +95,7 @@ struct SearchDev {
   int32_t hist_bins;
   int32_t tm;           // 32-template blocks per template tile (1 or 2)
   int32_t tn;           // 32-offset blocks per wave (4 or 8)
+  int32_t pipe;         // K-loop schedule: 0 blocked, 1 MFMA/load interleaved
   int32_t n_wg;         // offsets per work item = 4 * 32 * tn
   double hist_lo, hist_hi;
 };
@@ -119,7 +123,7 @@ hipError_t launch_prefix(const BatchHdr* hdr, int32_t seg_slots, hipStream_t s);
 hipError_t launch_norms(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks, int L,
                         int norm, hipStream_t s);
 hipError_t prepare_main(const BankDev& b, const SearchDev& p);
-bool main_variant_exists(int precision, int tm, int tn);
+bool main_variant_exists(int precision, int tm, int tn, int pipe);
 hipError_t launch_main(const BatchHdr* hdr, int64_t main_blocks, const BankDev& b,
                        const SearchDev& p, hipStream_t s);
 hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,

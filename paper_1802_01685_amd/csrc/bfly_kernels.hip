@@ -25,6 +25,7 @@ namespace bfly {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------------------
 // Small numeric helpers.
@@ -87,6 +88,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // BF16X3 layout, per (b, c): plane (hi, lo) x 64 lanes x 8 bf16, lane l = h*32 + m holding
 //   taps 16c + 8h + i (i = 0..7) of template 32b + m -- the A operand of one
 //   v_mfma_f32_32x32x16_bf16 step.
+// F16X2 layout: as BF16X3, with fp16 hi and lo of h * 2^10.
 // FP8 layout, per (b, 64-tap chunk c): 64 lanes x 32 e4m3 codes, lane l = h*32 + m holding
 //   taps 64c + 32h + i (i = 0..31) of template 32b + m -- the A operand of one
 //   v_mfma_scale_f32_32x32x64_f8f6f4; template k is stored as h_k * 2^e_k with e_k the
@@ -155,6 +157,17 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
       const int64_t base = ((int64_t)blk * b.n_chunks + c) * 2;
       out[((base + 0) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)hi) >> 16);
       out[((base + 1) * 64 + ln) * 8 + i] = (uint16_t)(__float_as_uint((float)lo) >> 16);
+    } else if (b.precision == P_F16X2) {
+      // same layout as BF16X3; fp16 hi + lo of h * 2^10 (keeps lo clear of subnormals)
+      const int c = n >> 4, r = n & 15;
+      const int ln = (r >> 3) * 32 + m, i = r & 7;
+      const double hs = ldexp(h, F16_TEMPLATE_EXP);
+      const _Float16 hi = (_Float16)hs;
+      const _Float16 lo = (_Float16)(hs - (double)hi);
+      _Float16* out = (_Float16*)dst;
+      const int64_t base = ((int64_t)blk * b.n_chunks + c) * 2;
+      out[((base + 0) * 64 + ln) * 8 + i] = hi;
+      out[((base + 1) * 64 + ln) * 8 + i] = lo;
     } else {
       const int c = n >> 6, r = n & 63;
       const int ln = (r >> 5) * 32 + m, i = r & 31;
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 // ---------------------------------------------------------------------------------------
 size_t main_lds_bytes(int precision, int L_pad, int n_wg) {
   const size_t S = (size_t)n_wg + (size_t)L_pad + STRIP_SLACK;
-  return precision == P_FP32 ? S * 4 : precision == P_FP8 ? S * 8 : S * 16;
+  return precision == P_FP32 ? S * 4 : (precision == P_FP8 || precision == P_F16X2) ? S * 8 : S * 16;
 }
 
 struct ItemCtx {
@@ -367,6 +380,10 @@ struct AFrag<P_BF16X3, MB> {
   uint4 v[MB][2];     // [block][plane hi/lo]
 };
 template <int MB>
+struct AFrag<P_F16X2, MB> {
+  uint4 v[MB][2];     // [block][plane hi/lo], fp16
+};
+template <int MB>
 struct AFrag<P_FP8, MB> {
   uint4 v[MB][2];     // 32 e4m3 codes per lane per block per chunk
 };
@@ -382,7 +399,7 @@ __device__ __forceinline__ void load_a(AFrag<PREC, MB>& f, const void* bank, int
       f.v[t][0] = A[idx];
       f.v[t][1] = A[idx + 1];
     }
-  } else if constexpr (PREC == P_BF16X3) {
+  } else if constexpr (PREC == P_BF16X3 || PREC == P_F16X2) {
     const uint4* A = (const uint4*)bank;
 #pragma unroll
     for (int t = 0; t < MB; ++t) {
@@ -420,6 +437,10 @@ template <int NB>
 struct BFrag<P_FP8, NB> {
   uint4 v[NB][2];     // [offset block][32 codes]
 };
+template <int NB>
+struct BFrag<P_F16X2, NB> {
+  uint4 v[NB][1];     // [offset block][8 fp16 samples]
+};
 
 // Strip fragments of chunk c for the offset blocks j in [J0, J1) (all by default).
 template <int PREC, int NB, int J0 = 0, int J1 = NB>
@@ -450,13 +471,15 @@ __device__ __forceinline__ void load_b(BFrag<PREC, NB>& f, const char* lds, int 
     }
   } else {
     // Block j and chunk c move the 4-sample cell by 8j and 4c: the address by 256j + 128c.
+    // BF16X3 reads the hi and lo planes, F16X2 its single plane.
+    constexpr int NPL = PREC == P_F16X2 ? 1 : 2;
     const int p0 = off_w + n + 8 * h;
     const int base = (p0 >> 2) * 32 + (p0 & 3) * 8 + 128 * c;
 #pragma unroll
     for (int j = J0; j < J1; ++j) {
       const int addr = base + 256 * j;
 #pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
+      for (int pl = 0; pl < NPL; ++pl) {
         const uint2 u0 = *(const uint2*)(lds + pl * plane_bytes + addr);
         const uint2 u1 = *(const uint2*)(lds + pl * plane_bytes + addr + 32);
         f.v[j][pl] = make_uint4(u0.x, u0.y, u1.x, u1.y);
@@ -486,6 +509,20 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[MB][NB], const AFrag<PRE
         const i32x8 bv = __builtin_bit_cast(i32x8, (U8{bf.v[j][0], bf.v[j][1]}));
         acc[t][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[t][j], 0, 0, 0,
                                                                     sa[t], 0, sb);
+      }
+    }
+  } else if constexpr (PREC == P_F16X2) {
+    // h_hi*x, then h_lo*x: consecutive MFMAs write different accumulators.
+#pragma unroll
+    for (int term = 0; term < 2; ++term) {
+#pragma unroll
+      for (int t = 0; t < MB; ++t) {
+        const f16x8 av = __builtin_bit_cast(f16x8, a.v[t][term]);
+#pragma unroll
+        for (int j = J0; j < J1; ++j) {
+          const f16x8 bv = __builtin_bit_cast(f16x8, bf.v[j][0]);
+          acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[t][j], 0, 0, 0);
+        }
       }
     }
   } else if constexpr (PREC == P_FP32) {
@@ -521,18 +558,21 @@ template <int NB>
 __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
                                           const SearchDev& p, int bin, const float (&binmax)[NB],
                                           const double (&inv)[NB], int64_t tau_w0, int n,
-                                          int h, int lane) {
+                                          int h, int lane, float dscale) {
   unsigned long long fix = 0ull;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const float v = fmaxf(binmax[j], __shfl_xor(binmax[j], 32, 64));
     const int64_t tau = tau_w0 + 32 * j + n;
     if (h == 0 && tau < sg.W && inv[j] > 0.0) {
-      const float s = (float)((double)v * inv[j]);
+      const float s = (float)((double)v * (double)dscale * inv[j]);
       if (sg.spec) {
-        unsigned int* dst =
-            (unsigned int*)sg.spec + (tau / p.t_block) * (int64_t)b.n_bins + bin;
-        atomicMax(dst, __float_as_uint(s));
+        // bin-major rows: the 32 lanes of a flush write 32 consecutive offsets of one row
+        const int64_t at = (int64_t)bin * sg.spec_rows + tau / p.t_block;
+        if (p.t_block == 1)
+          sg.spec[at] = s;                 // each (bin, offset) is owned by one lane
+        else
+          atomicMax((unsigned int*)sg.spec + at, __float_as_uint(s));  // s >= 0: bits order
       }
       fix += (unsigned long long)__double2ll_rn((double)s * SPEC_FIX_SCALE);
     }
@@ -546,8 +586,8 @@ __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
   if (lane == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
 }
 
-// One work item: strip fill, template sweep, flushes.
-template <int PREC, int MB, int NB>
+// One work item: strip fill, template sweep, flushes.  PIPE selects the K-loop schedule.
+template <int PREC, int MB, int NB, int PIPE>
 __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int64_t item,
                                           const BankDev& b, const SearchDev& p, char* lds) {
   const SegDesc* segs = hdr_segs(hdr);
@@ -577,7 +617,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 
   // ---- strip fill ----
   const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
-  int sb = 127;   // FP8: E8M0 scale undoing the strip's 2^e_x
+  int sb = 127;          // FP8: E8M0 scale undoing the strip's 2^e_x
+  float dscale = 1.0f;   // F16X2: 2^-(10 + e_x), undoing the template and strip scales
   if constexpr (PREC == P_FP32) {
     float* sx = (float*)lds;
     for (int i = tid; i < S; i += WG_THREADS) {
@@ -585,8 +626,10 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       float v = gi < sg.n ? sg.x[gi] : 0.0f;
       sx[i] = isfinite(v) ? v : 0.0f;
     }
-  } else if constexpr (PREC == P_FP8) {
-    // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= 448
+  } else if constexpr (PREC == P_FP8 || PREC == P_F16X2) {
+    // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= LIM
+    // (448 for e4m3, 2^14 for fp16)
+    constexpr float LIM = PREC == P_FP8 ? 448.0f : 16384.0f;
     __shared__ float wmax[WG_WAVES];
     float mx = 0.0f;
     for (int i = tid; i < S; i += WG_THREADS) {
@@ -599,25 +642,41 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     if (lane == 0) wmax[wave] = mx;
     __syncthreads();
     mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    int ex = mx > 0.0f ? (int)floorf(log2f(448.0f / mx)) : 0;
+    int ex = mx > 0.0f ? (int)floorf(log2f(LIM / mx)) : 0;
     ex = ex < -100 ? -100 : (ex > 100 ? 100 : ex);
-    while (ex > -100 && ldexpf(mx, ex) > 448.0f) --ex;   // guard log2f rounding
-    sb = 127 - ex;
-    // cell (q, c): codes of x[tau0 + 8q + c + e] * 2^e_x, e = 0..7
-    for (int t = tid; t < S; t += WG_THREADS) {
-      const int q = t >> 3, c = t & 7;
-      float v[8];
+    while (ex > -100 && ldexpf(mx, ex) > LIM) --ex;   // guard log2f rounding
+    if constexpr (PREC == P_FP8) {
+      sb = 127 - ex;
+      // cell (q, c): codes of x[tau0 + 8q + c + e] * 2^e_x, e = 0..7
+      for (int t = tid; t < S; t += WG_THREADS) {
+        const int q = t >> 3, c = t & 7;
+        float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t gi = tau0 + 8 * q + c + e;
-        float u = gi < sg.n ? sg.x[gi] : 0.0f;
-        v[e] = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+        for (int e = 0; e < 8; ++e) {
+          const int64_t gi = tau0 + 8 * q + c + e;
+          float u = gi < sg.n ? sg.x[gi] : 0.0f;
+          v[e] = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+        }
+        int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+        w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w0, true);
+        int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
+        w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], w1, true);
+        *(uint2*)(lds + t * 8) = make_uint2((unsigned)w0, (unsigned)w1);
       }
-      int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
-      w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w0, true);
-      int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
-      w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], w1, true);
-      *(uint2*)(lds + t * 8) = make_uint2((unsigned)w0, (unsigned)w1);
+    } else {
+      dscale = ldexpf(1.0f, -(F16_TEMPLATE_EXP + ex));
+      // cell (q, c): fp16 of x[tau0 + 4q + c + e] * 2^e_x, e = 0..3 (one plane)
+      for (int t = tid; t < S; t += WG_THREADS) {
+        const int q = t >> 2, c = t & 3;
+        _Float16 hv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t gi = tau0 + 4 * q + c + e;
+          float u = gi < sg.n ? sg.x[gi] : 0.0f;
+          hv[e] = (_Float16)(isfinite(u) ? ldexpf(u, ex) : 0.0f);
+        }
+        *(uint2*)(lds + t * 8) = __builtin_bit_cast(uint2, hv);
+      }
     }
   } else {
     // cell (q, c) of plane pl: samples x[tau0 + 4q + c + e], e = 0..3, as bf16 hi / lo.
@@ -683,7 +742,55 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     AFrag<PREC, MB> a0, a1;
     __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (NB <= 4) {
+    if constexpr (PIPE == 1) {
+      // Interleaved schedule.  The strip fragments live in two halves (offset blocks
+      // [0, H) and [H, NB)); region (c, h) issues the MFMAs of half h of chunk c and, between
+      // them, the LDS reads of the other half for the next region (half 1 of chunk c, or half
+      // 0 of chunk c + 1) and, in half 0, the template fragments of chunk c + 1.  A region's
+      // loads never write registers its own MFMAs read.
+      constexpr int H = NB / 2;
+      BFrag<PREC, NB> bb;
+      load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
+      load_b<PREC, NB, 0, H>(bb, lds, off_w, 0, n, h, plane_bytes);
+      __builtin_amdgcn_sched_barrier(0);
+      constexpr int NMF =
+          (PREC == P_BF16X3 ? 3 : PREC == P_F16X2 ? 2 : PREC == P_FP32 ? 8 : 1) * MB * H;
+      constexpr int NDS = (PREC == P_F16X2 ? 1 : PREC == P_FP32 ? 8 : 2) * H;  // LDS reads
+      constexpr int NVM = 2 * MB;                                                        // loads
+#define BFLY_INTERLEAVE(WITH_VMEM)                                                    \
+      do {                                                                            \
+        _Pragma("unroll") for (int i_ = 0; i_ < NDS; ++i_) {                          \
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                          \
+        }                                                                             \
+        if (WITH_VMEM) {                                                              \
+          _Pragma("unroll") for (int i_ = 0; i_ < NVM; ++i_) {                        \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                        \
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                        \
+          }                                                                           \
+        }                                                                             \
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);                          \
+        __builtin_amdgcn_sched_barrier(0);                                            \
+      } while (0)
+      for (int c = 0; c < nc; c += 2) {
+        const int c2 = c + 2 < nc ? c + 2 : nc - 1;
+        mma_chunk<PREC, MB, NB, 0, H>(acc, a0, bb, sa, sb);
+        load_b<PREC, NB, H, NB>(bb, lds, off_w, c, n, h, plane_bytes);
+        load_a<PREC, MB>(a1, b.data, blk0, c + 1, nc, lane);
+        BFLY_INTERLEAVE(true);
+        mma_chunk<PREC, MB, NB, H, NB>(acc, a0, bb, sa, sb);
+        load_b<PREC, NB, 0, H>(bb, lds, off_w, c + 1, n, h, plane_bytes);
+        BFLY_INTERLEAVE(false);
+        mma_chunk<PREC, MB, NB, 0, H>(acc, a1, bb, sa, sb);
+        load_b<PREC, NB, H, NB>(bb, lds, off_w, c + 1, n, h, plane_bytes);
+        load_a<PREC, MB>(a0, b.data, blk0, c2, nc, lane);
+        BFLY_INTERLEAVE(true);
+        mma_chunk<PREC, MB, NB, H, NB>(acc, a1, bb, sa, sb);
+        load_b<PREC, NB, 0, H>(bb, lds, off_w, c2, n, h, plane_bytes);
+        BFLY_INTERLEAVE(false);
+      }
+#undef BFLY_INTERLEAVE
+    } else if constexpr (NB <= 4) {
       // Two strip-fragment buffers: chunk c+1's fragments load while chunk c's MFMAs run.
       BFrag<PREC, NB> b0, b1;
       load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
@@ -748,7 +855,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     if (r_lo == 0 && r_hi == (32 * MB) && bA == bB) {
       // whole tile owned and inside one bin
       if (bA != cur_bin) {
-        if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+        if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
         cur_bin = bA;
 #pragma unroll
         for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
@@ -789,7 +896,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
           }
       for (int bn = bA; bn <= bB; ++bn) {
         if (bn != cur_bin) {
-          if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+          if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
           cur_bin = bn;
 #pragma unroll
           for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
@@ -810,7 +917,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       }
     }
   }
-  if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane);
+  if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
 
   // ---- per-offset maxima: combine the two row halves, then one atomic per offset ----
 #pragma unroll
@@ -825,7 +932,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     if (h == 0 && tau < sg.W && bestk[j] >= 0) {
       const unsigned int kg = (unsigned int)(b.k_offset + bestk[j]);
       const unsigned long long key =
-          ((unsigned long long)__float_as_uint(best[j]) << 32) | (0xFFFFFFFFull - kg);
+          ((unsigned long long)__float_as_uint(best[j] * dscale) << 32) | (0xFFFFFFFFull - kg);
       atomicMax(sg.mkey + tau, key);
     }
   }
@@ -834,55 +941,65 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 // Each work-group runs items blockIdx.x, blockIdx.x + gridDim.x, ...: one item per
 // work-group for a plain batch launch, a persistent loop for captured launches whose grid
 // is fixed while the batch changes.
-template <int PREC, int MB, int NB>
+template <int PREC, int MB, int NB, int PIPE>
 __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const BatchHdr* __restrict__ hdr,
                                                         BankDev b, SearchDev p) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int64_t n_items = hdr->n_items;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    main_item<PREC, MB, NB>(hdr, item, b, p, lds);
+    main_item<PREC, MB, NB, PIPE>(hdr, item, b, p, lds);
     __syncthreads();   // the next item refills the strip
   }
 }
 
-template <int PREC, int MB, int NB>
+template <int PREC, int MB, int NB, int PIPE>
 static hipError_t prepare_main_t(const BankDev& b) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  return hipFuncSetAttribute((const void*)k_main<PREC, MB, NB>,
+  return hipFuncSetAttribute((const void*)k_main<PREC, MB, NB, PIPE>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int PREC, int MB, int NB>
+template <int PREC, int MB, int NB, int PIPE>
 static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                 const SearchDev& p, hipStream_t s) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  hipLaunchKernelGGL((k_main<PREC, MB, NB>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
+  hipLaunchKernelGGL((k_main<PREC, MB, NB, PIPE>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
                      hdr, b, p);
   return hipGetLastError();
 }
 
-// The compiled tile shapes (template blocks x offset blocks per wave), per precision.
+// The compiled kernel variants: (template blocks, offset blocks per wave, K-loop schedule).
 #define BFLY_DISPATCH(FN, ...)                                                         \
   do {                                                                                 \
-    const int v_ = p.tm * 16 + p.tn;                                                   \
+    const int v_ = p.pipe * 256 + p.tm * 16 + p.tn;                                    \
     if (b.precision == P_FP32) {                                                       \
-      if (v_ == 2 * 16 + 4) return FN<P_FP32, 2, 4>(__VA_ARGS__);                      \
-      if (v_ == 1 * 16 + 8) return FN<P_FP32, 1, 8>(__VA_ARGS__);                      \
+      if (v_ == 0x024) return FN<P_FP32, 2, 4, 0>(__VA_ARGS__);                        \
+      if (v_ == 0x018) return FN<P_FP32, 1, 8, 0>(__VA_ARGS__);                        \
     } else if (b.precision == P_BF16X3) {                                              \
-      if (v_ == 2 * 16 + 4) return FN<P_BF16X3, 2, 4>(__VA_ARGS__);                    \
-      if (v_ == 1 * 16 + 8) return FN<P_BF16X3, 1, 8>(__VA_ARGS__);                    \
-      if (v_ == 2 * 16 + 8) return FN<P_BF16X3, 2, 8>(__VA_ARGS__);                    \
+      if (v_ == 0x024) return FN<P_BF16X3, 2, 4, 0>(__VA_ARGS__);                      \
+      if (v_ == 0x018) return FN<P_BF16X3, 1, 8, 0>(__VA_ARGS__);                      \
+      if (v_ == 0x028) return FN<P_BF16X3, 2, 8, 0>(__VA_ARGS__);                      \
+      if (v_ == 0x124) return FN<P_BF16X3, 2, 4, 1>(__VA_ARGS__);                      \
+      if (v_ == 0x128) return FN<P_BF16X3, 2, 8, 1>(__VA_ARGS__);                      \
+    } else if (b.precision == P_F16X2) {                                               \
+      if (v_ == 0x024) return FN<P_F16X2, 2, 4, 0>(__VA_ARGS__);                       \
+      if (v_ == 0x028) return FN<P_F16X2, 2, 8, 0>(__VA_ARGS__);                       \
+      if (v_ == 0x128) return FN<P_F16X2, 2, 8, 1>(__VA_ARGS__);                       \
     } else if (b.precision == P_FP8) {                                                 \
-      if (v_ == 2 * 16 + 4) return FN<P_FP8, 2, 4>(__VA_ARGS__);                       \
-      if (v_ == 1 * 16 + 8) return FN<P_FP8, 1, 8>(__VA_ARGS__);                       \
+      if (v_ == 0x024) return FN<P_FP8, 2, 4, 0>(__VA_ARGS__);                         \
+      if (v_ == 0x018) return FN<P_FP8, 1, 8, 0>(__VA_ARGS__);                         \
+      if (v_ == 0x128) return FN<P_FP8, 2, 8, 1>(__VA_ARGS__);                         \
     }                                                                                  \
     return hipErrorInvalidValue;                                                       \
   } while (0)
 
-bool main_variant_exists(int precision, int tm, int tn) {
-  const int v = tm * 16 + tn;
-  if (precision == P_BF16X3) return v == 36 || v == 24 || v == 40;
-  return v == 36 || v == 24;
+bool main_variant_exists(int precision, int tm, int tn, int pipe) {
+  const int v = pipe * 256 + tm * 16 + tn;
+  if (precision == P_BF16X3)
+    return v == 0x024 || v == 0x018 || v == 0x028 || v == 0x124 || v == 0x128;
+  if (precision == P_FP8) return v == 0x024 || v == 0x018 || v == 0x128;
+  if (precision == P_F16X2) return v == 0x024 || v == 0x028 || v == 0x128;
+  return v == 0x024 || v == 0x018;
 }
 
 // Sets the kernel's dynamic-LDS limit; call before launching (and before capturing).

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
 
 Tolerances (max relative error of the butterfly output m and of the spectrogram S over
-non-degenerate offsets): FP32 1e-5, BF16 hi/lo split 1e-4, FP8 (e4m3 with power-of-two
+non-degenerate offsets): FP32 1e-5, BF16 hi/lo split and FP16 template split 1e-4, FP8
+(e4m3 with power-of-two
 template and strip scales) 0.15, its measured bound.  Relative errors are taken
 against max(value, 1/sqrt(L)).  Argmax: the template the GPU
 reports must reach the FP64 maximum within 2*tol (so it must be the oracle's template
@@ -21,7 +22,7 @@ from synth import (BankParams, bank_params, cfg1_series, cfg2_series, cfg3_serie
 from tests.parity_util import TOL, check_against_oracle, check_hist, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-PRECS = ["fp32", "bf16x3", "fp8"]
+PRECS = ["fp32", "bf16x3", "f16x2", "fp8"]
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +99,7 @@ def test_small_shapes(bf, name, prec):
         assert st["n_degenerate"] > 0
     if t_block > 1:
         want = O.decimate(orc["S"], t_block)
-        got = g["spec"].astype(np.float64)
+        got = g["spec"].T.astype(np.float64)
         pos = want > 0
         floor = 1.0 / np.sqrt(p.L)
         assert np.all(np.abs(got[pos] - want[pos]) <= TOL[prec] * np.maximum(want[pos], floor))
@@ -177,7 +178,7 @@ def test_cfg2_full_size_sampled(bf, prec):
     # properties at every offset
     assert np.array_equal(g["hist"], O.histogram(g["max_abs"].astype(np.float64),
                                                  g["argmax"] < 0, 256, 0.0, 1.0))
-    spec = g["spec"].astype(np.float64)
+    spec = g["spec"].T.astype(np.float64)          # [offset][bin]
     assert np.array_equal(spec.max(axis=1), g["max_abs"].astype(np.float64))
     assert np.allclose(g["spectrum"] * W, spec.sum(axis=0), rtol=1e-9, atol=0)
     assert np.all(g["max_abs"] <= 1.0 + 1e-5)
@@ -208,7 +209,8 @@ def test_cfg3_share_with_control_sampled(bf, prec):
     assert np.array_equal(np.sort(x), np.sort(xc))
 
 
-SHAPES = {"fp32": ["2x4", "1x8"], "bf16x3": ["2x4", "1x8", "2x8"]}
+SHAPES = {"fp32": ["2x4", "1x8"], "bf16x3": ["2x4", "1x8", "2x8", "2x4i", "2x8i"],
+          "f16x2": ["2x4", "2x8", "2x8i"]}
 
 
 @pytest.mark.parametrize("prec,shape", [(p, s) for p in SHAPES for s in SHAPES[p]])
