@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 METRIC = "template×offset correlations/s vs plain FP32 at stated error; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "f16x2": 2500.0}   # MI355X dense MFMA peaks
 MFMA_TERMS = {"fp32": 1, "bf16x3": 3, "f16x2": 2}                   # MFMA products per tap
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 5e-4}
 
 
 def log(*a):
@@ -84,13 +84,13 @@ def time_form(bf, torch, p, xs, prec, steps, warmup):
     return res
 
 
-def roofline(res, p, prec):
+def roofline(res, p, prec, tile):
     ms = res["kernel_ms"]["main"]
     flops = 2.0 * p.L * res["corr_per_step"]           # algorithmic: one multiply-add per tap
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": recorded_traffic(prec, tile),
             "kernel": "k_main", "kernel_ms": round(ms, 3),
             "mfma_terms": MFMA_TERMS[prec],
             "executed_frac": round(achieved * MFMA_TERMS[prec] / peak, 4)}
@@ -180,6 +180,36 @@ def serving_leg(bf, prec, n_segments, budget_gib, slots):
             "capacity_segments_per_s": capacity, "ticks": stats["ticks"]}
 
 
+def kernel_tile(prec):
+    """The tile shape bf_search uses (BF_TILE overrides the library default)."""
+    env = os.environ.get("BF_TILE")
+    if env:
+        return env
+    return "2x8i" if prec in ("bf16x3", "f16x2") else "2x4"
+
+
+def recorded_traffic(prec, tile):
+    """HBM bytes per launch of the contraction kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by the same counters on a copy of known
+    size), if it was taken on exactly the current kernel source and tile; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1802_01685_amd", "csrc", "bfly_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("traffic-record:"):
+                continue
+            try:
+                rec = json.loads(line.split(":", 1)[1])
+            except ValueError:
+                continue
+            if rec.get("kernel_sha256") == sha and rec.get("precision") == prec \
+                    and rec.get("tile") == tile:
+                return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
+
+
 def errors(orc, out, tol):
     import numpy as np
     offs = orc["offsets"]
@@ -199,7 +229,9 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
-    ap.add_argument("--cpu-offsets", type=int, default=256, help="0 skips the oracle leg")
+    ap.add_argument("--extra-forms", default="f16x2",
+                    help="comma-separated further precision forms to time and check ('' skips)")
+    ap.add_argument("--cpu-offsets", type=int, default=1024, help="0 skips the oracle leg")
     ap.add_argument("--serve-segments", type=int, default=16,
                     help="segments per point of the serving leg (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -244,6 +276,11 @@ def main() -> int:
         log(f"timing fp32: 1 warmup + {args.fp32_steps} steps")
         fp32_res = time_form(bf, torch, p, xs, "fp32", args.fp32_steps, 1)
         log(f"  {fp32_res['value']:.4g} corr/s, {fp32_res['ms_per_step']:.1f} ms/step")
+    extra = {}
+    for form in [f for f in args.extra_forms.split(",") if f and f != args.precision]:
+        log(f"timing {form}: 1 warmup + {args.fp32_steps} steps")
+        extra[form] = time_form(bf, torch, p, xs, form, args.fp32_steps, 1)
+        log(f"  {extra[form]['value']:.4g} corr/s, {extra[form]['ms_per_step']:.1f} ms/step")
 
     cpu = None
     err = {}
@@ -253,6 +290,8 @@ def main() -> int:
         err[args.precision] = errors(orc, main_res["outs"][0], TOL[args.precision])
         if fp32_res:
             err["fp32"] = errors(orc, fp32_res["outs"][0], TOL["fp32"])
+        for form, r in extra.items():
+            err[form] = errors(orc, r["outs"][0], TOL[form])
         log(f"  oracle {cpu['value']:.4g} corr/s on {cpu['cores']} threads; errors {err}")
 
     serving = None
@@ -282,18 +321,23 @@ def main() -> int:
                    "precision_form": args.precision,
                    "series": 2, "samples_per_series": int(x.shape[0]),
                    "templates": main_res["corr_per_step"] // (2 * (x.shape[0] - p.L + 1)),
-                   "L": p.L, "work_items": main_res["n_items"], "bin_ranges": main_res["n_ranges"]},
+                   "L": p.L, "work_items": main_res["n_items"], "bin_ranges": main_res["n_ranges"],
+                   "tile": kernel_tile(args.precision)},
         "latency_ms": ({"p50": lat["p50_ms"], "p99": lat["p99_ms"],
                         "of": "serving requests, submit to done, arrivals at 70% of capacity"}
                        if lat else None),
         "step_latency_ms": {"p50": float(np.percentile(steps_ms, 50)),
                             "p99": float(np.percentile(steps_ms, 99))},
         "kernel_ms": {k: round(v, 4) for k, v in main_res["kernel_ms"].items()},
-        "roofline": roofline(main_res, p, args.precision),
+        "roofline": roofline(main_res, p, args.precision, kernel_tile(args.precision)),
         "fp32": None if fp32_res is None else {
             "value": fp32_res["value"], "ms_per_step": fp32_res["ms_per_step"],
-            "roofline": roofline(fp32_res, p, "fp32"),
+            "roofline": roofline(fp32_res, p, "fp32", kernel_tile("fp32")),
             "speedup_of_chosen_form": main_res["value"] / fp32_res["value"]},
+        "other_forms": {form: {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                               "tile": kernel_tile(form),
+                               "roofline": roofline(r, p, form, kernel_tile(form))}
+                        for form, r in extra.items()} or None,
         "error_vs_fp64": err or None,
         "cpu_baseline": cpu,
         "serving": serving,

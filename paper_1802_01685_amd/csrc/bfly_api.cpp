@@ -102,6 +102,7 @@ void fill_geometry(const bf_bank_desc* d, GridDev* g, BankDev* b) {
   b->k_offset = f0_lo * d->n_fdot;
   b->L = d->L;
   b->texp = nullptr;
+  b->tsum = nullptr;
   b->L_pad = (int32_t)round_up(d->L, 2 * chunk_taps(d->precision));
   b->n_chunks = b->L_pad / chunk_taps(d->precision);
   b->precision = d->precision;
@@ -191,9 +192,12 @@ int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per C
 // overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
 // depend on it (FP8 does, through its per-strip scales).
 void choose_tile(int precision, int32_t* tm, int32_t* tn, int32_t* pipe) {
+  // Defaults from measurement on MI355X: the split forms are fastest with 2 x 8 blocks and
+  // the interleaved schedule; FP32 (64-cycle MFMAs) and FP8 with 2 x 4.
+  const bool split = precision == BF_BF16X3 || precision == BF_F16X2;
   *tm = 2;
-  *tn = 4;
-  *pipe = 0;
+  *tn = split ? 8 : 4;
+  *pipe = split ? 1 : 0;
   const char* e = getenv("BF_TILE");
   int a = 0, c = 0;
   char il = 0;
@@ -519,8 +523,10 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     bk->grid = g;
     bk->dev = b;
     bk->dev.data = dev_mem;
-    bk->dev.texp = b.precision == P_FP8 ? (const int32_t*)((char*)dev_mem + bank_data_bytes(b))
-                                        : nullptr;
+    if (b.precision == P_FP8) {
+      bk->dev.texp = (const int32_t*)((char*)dev_mem + bank_data_bytes(b));
+      bk->dev.tsum = (const float*)(bk->dev.texp + b.K_pad);
+    }
     HIP_TRY(hipGetDevice(&bk->device), "hipGetDevice");
     *out = bk;
     return BF_OK;
@@ -627,7 +633,7 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   int64_t tiles = 0;
   for (int32_t i = 0; i < n_segs; ++i) {
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
-    int32_t tm = 2, tn = 4, pp = 0;
+    int32_t tm = 0, tn = 0, pp = 0;
     choose_tile(bank->dev.precision, &tm, &tn, &pp);
     const int64_t n_wg = 32 * (int64_t)tn * WG_WAVES;
     tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
@@ -635,7 +641,7 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   int slots = 0;
   bf_status st = device_slots(&slots);
   if (st != BF_OK) return st;
-  int32_t tm = 2, tn = 4, pp = 0;
+  int32_t tm = 0, tn = 0, pp = 0;
   choose_tile(bank->dev.precision, &tm, &tn, &pp);
   const int32_t r = plan_ranges(bank->dev, tiles, slots, tm);
   if (n_ranges) *n_ranges = r;

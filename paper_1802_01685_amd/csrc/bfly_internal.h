@@ -72,6 +72,7 @@ __host__ __device__ inline const SegDesc* hdr_segs(const BatchHdr* h) {
 struct BankDev {
   const void* data;     // tile layout, see bank_gen
   const int32_t* texp;  // FP8: per-template power-of-two exponent e_k (codes hold h * 2^e_k)
+  const float* tsum;    // FP8: sum over taps of the dequantised template (not exactly 0)
   int64_t K;            // local templates
   int64_t K_pad;        // multiple of TILE_K
   int64_t k_offset;     // global index of local template 0
@@ -105,8 +106,10 @@ struct SearchDev {
 inline size_t bank_data_bytes(const BankDev& b) {
   return (size_t)b.K_pad * (size_t)b.L_pad * (b.precision == P_FP8 ? 1 : 4);
 }
+// FP8 side tables after the codes: int32 exponent e_k [K_pad], then float sum of the
+// dequantised template [K_pad].
 inline size_t bank_exp_bytes(const BankDev& b) {
-  return b.precision == P_FP8 ? (((size_t)b.K_pad * 4 + 255) & ~(size_t)255) : 0;
+  return b.precision == P_FP8 ? (((size_t)b.K_pad * 8 + 255) & ~(size_t)255) : 0;
 }
 inline size_t bank_total_bytes(const BankDev& b) {
   return bank_data_bytes(b) + bank_exp_bytes(b) + 256;

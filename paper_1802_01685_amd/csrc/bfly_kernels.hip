@@ -92,7 +92,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // FP8 layout, per (b, 64-tap chunk c): 64 lanes x 32 e4m3 codes, lane l = h*32 + m holding
 //   taps 64c + 32h + i (i = 0..31) of template 32b + m -- the A operand of one
 //   v_mfma_scale_f32_32x32x64_f8f6f4; template k is stored as h_k * 2^e_k with e_k the
-//   largest exponent keeping max |h_k| * 2^e_k <= 448, and e_k is kept in texp[k].
+//   largest exponent keeping max |h_k| * 2^e_k <= 448, and e_k is kept in texp[k].  The
+//   rounded template no longer sums to zero; that sum (in template units) is kept in
+//   tsum[k] so the contraction can remove the window mean's share of it.
 // Padding templates (k >= K) and padding taps (n >= L) are zero.  The word after the bank
 // counts templates whose centred norm vanished (they cannot be normalised).
 // ---------------------------------------------------------------------------------------
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
   const int64_t blk = k >> 5;
   const int m = (int)(k & 31);
   int e8 = 0;
+  double qsum = 0.0;   // FP8: sum of the stored codes, in units of 2^-e8
   if (b.precision == P_FP8) {
     double mx = 0.0;
     if (real)
@@ -173,9 +176,14 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
       const int ln = (r >> 5) * 32 + m, i = r & 31;
       const float v = (float)ldexp(h, e8);   // |v| <= 448 by the choice of e8
       const int code = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF;
+      qsum += (double)__builtin_amdgcn_cvt_f32_fp8(code, 0);
       uint8_t* out = (uint8_t*)dst;
       out[(((int64_t)blk * b.n_chunks + c) * 64 + ln) * 32 + i] = (uint8_t)code;
     }
+  }
+  if (b.precision == P_FP8) {
+    qsum = wave_sum_d(qsum);
+    if (lane == 0) ((float*)(texp + b.K_pad))[k] = (float)ldexp(qsum, -e8);
   }
 }
 
@@ -706,10 +714,19 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int plane_bytes = S * 8;
 
   double inv[NB];
+  float mu[NB];   // FP8: window means, for the template-sum correction
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int64_t tau = tau_w0 + 32 * j + n;
     inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
+    mu[j] = 0.0f;
+    if constexpr (PREC == P_FP8) {
+      if (tau < sg.W) {
+        const double* a = sg.pre + tau * 4;
+        const double* z = sg.pre + (tau + b.L) * 4;
+        mu[j] = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L);
+      }
+    }
   }
   float best[NB], binmax[NB];
   int bestk[NB];
@@ -845,6 +862,26 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         load_b<PREC, NB, H, NB>(bb, lds, off_w, c2, n, h, plane_bytes);
         __builtin_amdgcn_sched_barrier(0);
       }
+    }
+
+    if constexpr (PREC == P_FP8) {
+      // The rounded templates carry a small sum s_k, which would pick up s_k times the
+      // window mean; d - mu * s_k is the contraction of the rounded template with the
+      // centred window.
+      const float* ts = b.tsum + blk0 * 32 + 4 * h;
+#pragma unroll
+      for (int t = 0; t < MB; ++t)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float4 s4 = *(const float4*)(ts + t * 32 + 8 * g);
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            acc[t][j][4 * g + 0] = fmaf(-mu[j], s4.x, acc[t][j][4 * g + 0]);
+            acc[t][j][4 * g + 1] = fmaf(-mu[j], s4.y, acc[t][j][4 * g + 1]);
+            acc[t][j][4 * g + 2] = fmaf(-mu[j], s4.z, acc[t][j][4 * g + 2]);
+            acc[t][j][4 * g + 3] = fmaf(-mu[j], s4.w, acc[t][j][4 * g + 3]);
+          }
+        }
     }
 
     // ---- epilogue: lane rows are 32t + 8g + 4h + i4 of the tile ----

@@ -6,10 +6,14 @@ import numpy as np
 
 from oracle import bfly_oracle as O
 
-# FP32 and the BF16 split: the bounds stated for the method.  FP8 (e4m3, 3 mantissa bits):
-# the measured bound, stated as a number -- each product carries a ~2.5% rounding error and
-# quantised templates are no longer exactly zero-mean, so a window's local mean leaks in.
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-4, "fp8": 0.15}
+# FP32 and the BF16 split: the bounds stated for the method.  The FP16 template split keeps
+# the data as one fp16 (11-bit significand): each sample carries up to 2^-11 relative
+# rounding, measured at 1.1e-4 to 2.3e-4 relative on m; its stated bound is 5e-4.
+# FP8 (e4m3, 3 mantissa bits): a stated number.  Template and data
+# codes each carry up to 2^-4 relative rounding, so a correlation carries a random error of
+# about 0.05 / sqrt(L) in rho: about 1% of m at the median, and up to ~7% of m (~15% of a
+# small spectrogram entry, relative to the 1/sqrt(L) floor) on templates of 37-64 taps.
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 5e-4, "fp8": 0.2}
 
 
 def to_np(out: dict) -> dict:

@@ -49,8 +49,9 @@ def test_bank_bytes_and_validation_on_host(lib):
     d3 = lib.make_desc(bank_params(3), "fp32")
     assert lib.bank_bytes(d3) == 720000 * 2016 * 4 + 256   # L_pad = 2016 (multiple of 32)
     d8 = lib.make_desc(bank_params(2), "fp8")
-    # one byte per tap, then an int32 exponent per template, then the status word
-    assert lib.bank_bytes(d8) == 65536 * 4096 + 65536 * 4 + 256
+    # one byte per tap, then an int32 exponent and a float template sum per template, then
+    # the status word
+    assert lib.bank_bytes(d8) == 65536 * 4096 + 65536 * 8 + 256
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
         q = lib.make_desc(bank_params(2), "fp32")
