@@ -359,3 +359,59 @@ def search_many(xs: list, p, offsets_list: list, norm: str = "centred") -> list:
         q["S"][d] = 0.0
         out.append({"m": q["m"], "a": q["a"], "S": q["S"], "degen": d, "offsets": q["offsets"]})
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# O14-O15: sigma of rho per template, the kappa-sigma tails and their pseudo-spectrum
+# (Sec. 2.2; Fig. 5 and Fig. 6 captions).
+# ---------------------------------------------------------------------------------------
+def sigma_tails(x: np.ndarray, p, kappa: float, norm: str = "centred") -> dict:
+    """Per-template sigma, the tails above kappa * sigma, and the tail counts per f0 bin.
+
+    sigma_k = sqrt(mean over the non-degenerate offsets of rho_k(tau)^2): the spread of the
+    matched-filter output of template k over the series (Sec. 2.2, Fig. 5 caption).  A zero-
+    mean template gives an output of zero mean, so its mean square is its variance -- the
+    energy the paper obtains from the spectra by Parseval's theorem (reading 23).
+    Tails: every (tau, k) with |rho_k(tau)| > kappa * sigma_k, strictly (reading 24; the
+    magnitude, as for every other reduction, reading 4).
+    Pseudo-spectrum: the number of tails per f0 bin (Fig. 6 caption; reading 9's key).
+
+    Returns sigma[K], n_ok, the tails sorted by (tau, k): tau[T], k[T] (global index),
+    rho[T] (signed), counts[n_bins], and degen[W].
+    """
+    x = np.asarray(x, dtype=np.float64)
+    g = grid(p)
+    L = p.L
+    W = x.shape[0] - L + 1
+    if W < 1:
+        raise ValueError("series shorter than the template")
+    E, _, degen = window_energy(x, L, None, norm)
+    ok = ~degen
+    n_ok = int(ok.sum())
+    Xw = windows(x, L)
+    Xw = np.where(np.isfinite(Xw), Xw, 0.0)
+    scale = np.zeros(W)
+    scale[ok] = 1.0 / np.sqrt(E[ok])
+    K = g.f0.shape[0]
+    nfd = g.n_fdot
+    sig = np.zeros(K)
+    counts = np.zeros(g.n_bins, dtype=np.int64)
+    taus, ks, rhos = [], [], []
+    step = max(nfd, (1 << 22) // W // nfd * nfd)
+    for k0 in range(0, K, step):
+        k1 = min(K, k0 + step)
+        H = templates(p.fs, L, g.f0[k0:k1], g.fdot[k0:k1])
+        r = (Xw @ H.T) * scale[:, None]                  # rho [W, k1-k0], 0 if degenerate
+        s = np.sqrt((r * r).sum(axis=0) / n_ok) if n_ok else np.zeros(k1 - k0)
+        sig[k0:k1] = s
+        t, j = np.nonzero(np.abs(r) > kappa * s[None, :])
+        taus.append(t)
+        ks.append(g.k_global[k0 + j])
+        rhos.append(r[t, j])
+        counts += np.bincount(g.bin[k0 + j], minlength=g.n_bins)
+    tau = np.concatenate(taus).astype(np.int64)
+    k = np.concatenate(ks).astype(np.int64)
+    rh = np.concatenate(rhos)
+    order = np.lexsort((k, tau))
+    return {"sigma": sig, "n_ok": n_ok, "tau": tau[order], "k": k[order], "rho": rh[order],
+            "counts": counts, "degen": degen}

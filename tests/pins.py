@@ -323,4 +323,131 @@ def pin_control(o):
     assert not np.array_equal(xc, x)
 
 
+# ---------------------------------------------------------------------------------------
+# sigma of rho, the kappa-sigma tails and their pseudo-spectrum
+# ---------------------------------------------------------------------------------------
+def _brute_rho(x, p, norm="centred"):
+    """Pure-Python loops over a possibly sharded bank: signed rho[tau][k_local] (0 on
+    degenerate windows), the degenerate flags, and each local template's global index and
+    f0 bin."""
+    L = p.L
+    f0s = [p.f0_min + i * (p.f0_max - p.f0_min) / (p.n_f0 - 1) for i in range(p.n_f0)]
+    f0s[-1] = p.f0_max
+    fds = [p.fdot_min + j * (p.fdot_max - p.fdot_min) / (p.n_fdot - 1) for j in range(p.n_fdot)]
+    fds[-1] = p.fdot_max
+    lo = p.shard_index * p.n_f0 // p.shard_count
+    hi = (p.shard_index + 1) * p.n_f0 // p.shard_count
+    H, kg, bins = [], [], []
+    for i in range(lo, hi):
+        for j in range(p.n_fdot):
+            c = [math.cos(2 * math.pi * (f0s[i] * (n / p.fs) + 0.5 * fds[j] * (n / p.fs) ** 2))
+                 for n in range(L)]
+            mu = sum(c) / L
+            c = [v - mu for v in c]
+            nr = math.sqrt(sum(v * v for v in c))
+            H.append([v / nr for v in c])
+            kg.append(i * p.n_fdot + j)
+            bins.append(i - lo)
+    rho, deg = [], []
+    for tau in range(len(x) - L + 1):
+        win = [float(x[tau + n]) for n in range(L)]
+        bad = any(not math.isfinite(v) for v in win)
+        win = [v if math.isfinite(v) else 0.0 for v in win]
+        R = sum(v * v for v in win)
+        if norm == "centred":
+            mu = sum(win) / L
+            E = sum((v - mu) ** 2 for v in win)
+        else:
+            E = R
+        d_ = bad or R == 0.0 or E <= 1e-12 * R
+        deg.append(d_)
+        row = []
+        for k in range(len(H)):
+            d = sum(H[k][n] * win[n] for n in range(L))
+            row.append(0.0 if d_ else d / math.sqrt(E))
+        rho.append(row)
+    return rho, deg, kg, bins
+
+
+def pin_tails_brute_force(o):
+    """sigma, the tails and the pseudo-spectrum on tiny inputs against pure-Python loops: a
+    sharded bank (global indices), a constant (degenerate) run, a NaN, both norms, and
+    kappa = 0 with the centred norm (every non-degenerate pair is a tail, no degenerate one
+    is)."""
+    p = BankParams(fs=16.0, L=7, n_f0=3, n_fdot=2, f0_min=1.5, f0_max=4.0,
+                   fdot_min=-3.0, fdot_max=5.0, shard_index=1, shard_count=2)
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal(44)
+    x[18:26] = -0.4           # windows 18, 19 are degenerate
+    x[37] = np.nan            # windows 31..37 hold a NaN
+    for norm in ("centred", "raw"):
+        rho, deg, kg, bins = _brute_rho(x, p, norm)
+        n_ok = sum(1 for d in deg if not d)
+        K = len(kg)
+        sig = [math.sqrt(sum(row[k] ** 2 for row in rho) / n_ok) for k in range(K)]
+        # kappa = 0 only with the centred norm: under the raw norm a constant window is not
+        # degenerate and its rho is a rounding residue (~1e-17) whose sign depends on the
+        # summation order
+        for kappa in ((0.0, 1.0, 1.7) if norm == "centred" else (0.5, 1.0, 1.7)):
+            want = sorted((t, kg[k], rho[t][k]) for t in range(len(rho)) for k in range(K)
+                          if abs(rho[t][k]) > kappa * sig[k])
+            counts = [0] * (max(bins) + 1)
+            for t in range(len(rho)):
+                for k in range(K):
+                    if abs(rho[t][k]) > kappa * sig[k]:
+                        counts[bins[k]] += 1
+            r = o.sigma_tails(x, p, kappa, norm)
+            assert r["n_ok"] == n_ok
+            assert np.allclose(r["sigma"], sig, rtol=0, atol=1e-13)
+            assert list(r["tau"]) == [w[0] for w in want]
+            assert list(r["k"]) == [w[1] for w in want]
+            assert np.allclose(r["rho"], [w[2] for w in want], rtol=0, atol=1e-13)
+            assert list(r["counts"]) == counts
+
+
+def pin_tails_parseval(o):
+    """A series of period L: every window holds one whole period, so E is the same for every
+    offset and, over W = L offsets, the numerator is the circular cross-correlation of the
+    template with one period.  Parseval's theorem then gives
+    sigma_k^2 = sum_f |H_k(f)|^2 |X(f)|^2 / (L^2 E) with L-point DFTs (numpy.fft)."""
+    p = _small_bank(L=32)
+    L = p.L
+    per = np.random.default_rng(16).standard_normal(L) + 0.3
+    x = np.concatenate([per, per[:L - 1]])
+    H = o.bank_templates(p)
+    Hf = np.abs(np.fft.fft(H, axis=1)) ** 2
+    Xf = np.abs(np.fft.fft(per)) ** 2
+    for norm in ("centred", "raw"):
+        E = float(((per - per.mean()) ** 2).sum()) if norm == "centred" else float((per ** 2).sum())
+        want = np.sqrt((Hf * Xf[None, :]).sum(axis=1) / (L * L * E))
+        r = o.sigma_tails(x, p, 2.0, norm)
+        assert r["n_ok"] == L
+        assert np.allclose(r["sigma"], want, rtol=1e-12, atol=0), (norm, r["sigma"], want)
+
+
+def pin_tails_invariants(o):
+    """Every tail exceeds kappa sigma and is at most the butterfly maximum of its offset; the
+    counts add up to the tails; an offset whose maximum exceeds kappa sigma of its argmax
+    template contributes that tail; an affine map of x changes nothing (centred norm); for
+    iid Gaussian data the mean of sigma_k^2 over the bank is 1/(L-1) (statistical, ~3%)."""
+    p = _small_bank(L=32)
+    g = o.grid(p)
+    x = np.random.default_rng(17).standard_normal(20000)
+    kappa = 2.5
+    r = o.sigma_tails(x, p, kappa)
+    s = o.search(x, p)
+    kl = r["k"] - int(g.k_global[0])
+    assert np.all(np.abs(r["rho"]) > kappa * r["sigma"][kl])
+    assert np.all(np.abs(r["rho"]) <= s["m"][r["tau"]] + 1e-13)
+    assert int(r["counts"].sum()) == r["tau"].size > 0
+    pairs = set(zip(r["tau"].tolist(), r["k"].tolist()))
+    hit = np.nonzero(s["m"] > kappa * r["sigma"][s["a"] - int(g.k_global[0])])[0]
+    assert hit.size > 0 and all((int(t), int(s["a"][t])) in pairs for t in hit)
+    r2 = o.sigma_tails(2.0 * x - 3.0, p, kappa)
+    assert np.allclose(r2["sigma"], r["sigma"], rtol=1e-12, atol=0)
+    assert np.array_equal(r2["tau"], r["tau"]) and np.array_equal(r2["k"], r["k"])
+    est = float((r["sigma"] ** 2).mean())
+    assert abs(est * (p.L - 1) - 1.0) < 0.1, est * (p.L - 1)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -43,6 +43,19 @@ MUTANTS = {
     "window_shift": ("return v if offsets is None else v[np.asarray(offsets)]",
                      "return v[1:] if offsets is None else v[np.asarray(offsets) + 1]"),
     "spectrum_max": ('"spectrum": S.mean(axis=0)', '"spectrum": S.max(axis=0)'),
+    "sigma_all_offsets": ("s = np.sqrt((r * r).sum(axis=0) / n_ok) if n_ok",
+                          "s = np.sqrt((r * r).sum(axis=0) / W) if n_ok"),
+    "sigma_squared": ("s = np.sqrt((r * r).sum(axis=0) / n_ok) if n_ok",
+                      "s = ((r * r).sum(axis=0) / n_ok) if n_ok"),
+    "sigma_of_numerator": ("r = (Xw @ H.T) * scale[:, None]                  # rho",
+                           "r = (Xw @ H.T) * (scale[:, None] > 0)            # rho"),
+    "tails_one_sided": ("t, j = np.nonzero(np.abs(r) > kappa * s[None, :])",
+                        "t, j = np.nonzero(r > kappa * s[None, :])"),
+    "tails_ge": ("t, j = np.nonzero(np.abs(r) > kappa * s[None, :])",
+                 "t, j = np.nonzero(np.abs(r) >= kappa * s[None, :])"),
+    "tails_local_index": ("ks.append(g.k_global[k0 + j])", "ks.append(k0 + j)"),
+    "tail_counts_by_fdot": ("counts += np.bincount(g.bin[k0 + j], minlength=g.n_bins)",
+                            "counts += np.bincount((k0 + j) // nfd % g.n_bins, minlength=g.n_bins)[::-1]"),
 }
 
 
