@@ -415,3 +415,46 @@ def sigma_tails(x: np.ndarray, p, kappa: float, norm: str = "centred") -> dict:
     order = np.lexsort((k, tau))
     return {"sigma": sig, "n_ok": n_ok, "tau": tau[order], "k": k[order], "rho": rh[order],
             "counts": counts, "degen": degen}
+
+
+# ---------------------------------------------------------------------------------------
+# O16: two-detector coincidence of tails (Fig. 6 caption).
+# ---------------------------------------------------------------------------------------
+def template_f0(p, k_global: np.ndarray) -> np.ndarray:
+    """Start frequency f0 of global template indices (reading 5: inclusive f0-major grid)."""
+    i = np.asarray(k_global, dtype=np.int64) // p.n_fdot
+    f0_axis = np.linspace(p.f0_min, p.f0_max, p.n_f0)
+    return f0_axis[i]
+
+
+def coincidences(tails_a: dict, tails_b: dict, p, dtau: int, df: float) -> dict:
+    """Tails of two simultaneous channels (e.g. two detectors) searched with the same bank.
+
+    A tail (tau, k) of channel A is coincident when channel B has a tail (tau', k') with
+    |tau - tau'| <= dtau and |f0(k) - f0(k')| <= df (reading 25: "simultaneous" means within
+    dtau offsets, the frequency key is the template's f0).  Returns, per f0 bin, the number
+    of coincident tails of A (counts_a) and of B (counts_b) -- the pseudo-spectra by
+    simultaneous counts -- and the number of coincident pairs.
+    Plain double loop over the two lists, grouped by offset.
+    """
+    g = grid(p)
+    ta, ka = np.asarray(tails_a["tau"], np.int64), np.asarray(tails_a["k"], np.int64)
+    tb, kb = np.asarray(tails_b["tau"], np.int64), np.asarray(tails_b["k"], np.int64)
+    fa, fb = template_f0(p, ka), template_f0(p, kb)
+    lo = int(g.k_global[0]) // p.n_fdot                    # first f0 index of the share
+    hit_a = np.zeros(ta.shape[0], dtype=bool)
+    hit_b = np.zeros(tb.shape[0], dtype=bool)
+    n_pairs = 0
+    by_tau = {}
+    for j, t in enumerate(tb.tolist()):
+        by_tau.setdefault(t, []).append(j)
+    for i in range(ta.shape[0]):
+        for t in range(int(ta[i]) - dtau, int(ta[i]) + dtau + 1):
+            for j in by_tau.get(t, ()):
+                if abs(fa[i] - fb[j]) <= df:
+                    hit_a[i] = True
+                    hit_b[j] = True
+                    n_pairs += 1
+    counts_a = np.bincount(ka[hit_a] // p.n_fdot - lo, minlength=g.n_bins).astype(np.int64)
+    counts_b = np.bincount(kb[hit_b] // p.n_fdot - lo, minlength=g.n_bins).astype(np.int64)
+    return {"counts_a": counts_a, "counts_b": counts_b, "n_pairs": n_pairs}

@@ -450,4 +450,71 @@ def pin_tails_invariants(o):
     assert abs(est * (p.L - 1) - 1.0) < 0.1, est * (p.L - 1)
 
 
+# ---------------------------------------------------------------------------------------
+# two-detector coincidence of tails
+# ---------------------------------------------------------------------------------------
+def _brute_coincidences(ta, ka, tb, kb, p, dtau, df):
+    """Pure-Python pairwise loops over unsorted lists; f0 from the linspace formula."""
+    f0s = [p.f0_min + i * (p.f0_max - p.f0_min) / (p.n_f0 - 1) for i in range(p.n_f0)]
+    f0s[-1] = p.f0_max
+    lo = p.shard_index * p.n_f0 // p.shard_count
+    nb = (p.shard_index + 1) * p.n_f0 // p.shard_count - lo
+    ca, cb = [0] * nb, [0] * nb
+    hb = [False] * len(tb)
+    pairs = 0
+    for i in range(len(ta)):
+        hit = False
+        for j in range(len(tb)):
+            if abs(ta[i] - tb[j]) <= dtau and \
+                    abs(f0s[ka[i] // p.n_fdot] - f0s[kb[j] // p.n_fdot]) <= df:
+                hit = True
+                hb[j] = True
+                pairs += 1
+        if hit:
+            ca[ka[i] // p.n_fdot - lo] += 1
+    for j in range(len(tb)):
+        if hb[j]:
+            cb[kb[j] // p.n_fdot - lo] += 1
+    return ca, cb, pairs
+
+
+def pin_coincidence_brute_force(o):
+    """Random tail lists of two channels on a sharded bank against pure-Python pairwise
+    loops, for several offset windows and frequency widths, including a width equal to
+    the f0 spacing (pairs exactly df apart count)."""
+    p = BankParams(fs=256.0, L=40, n_f0=9, n_fdot=5, f0_min=10.0, f0_max=70.0,
+                   fdot_min=-20.0, fdot_max=20.0, shard_index=1, shard_count=2)
+    lo = 1 * 9 // 2
+    hi = 2 * 9 // 2
+    rng = np.random.default_rng(18)
+    ka = rng.integers(lo * 5, hi * 5, 60)
+    kb = rng.integers(lo * 5, hi * 5, 50)
+    ta = rng.integers(0, 30, 60)
+    tb = rng.integers(0, 30, 50)
+    for dtau, df in ((0, 0.0), (0, 7.5), (2, 7.5), (1, 16.0), (5, 100.0)):
+        r = o.coincidences({"tau": ta, "k": ka}, {"tau": tb, "k": kb}, p, dtau, df)
+        ca, cb, pairs = _brute_coincidences(ta.tolist(), ka.tolist(), tb.tolist(), kb.tolist(),
+                                            p, dtau, df)
+        assert list(r["counts_a"]) == ca and list(r["counts_b"]) == cb, (dtau, df)
+        assert r["n_pairs"] == pairs, (dtau, df)
+
+
+def pin_coincidence_limits(o):
+    """Swapping the channels swaps the counts; a channel against itself with dtau = 0 and
+    df = 0 makes every tail coincident with itself; an empty channel makes none."""
+    p = _small_bank()
+    rng = np.random.default_rng(19)
+    a = {"tau": rng.integers(0, 50, 40), "k": rng.integers(0, 12, 40)}
+    b = {"tau": rng.integers(0, 50, 30), "k": rng.integers(0, 12, 30)}
+    r1 = o.coincidences(a, b, p, 1, 7.5)
+    r2 = o.coincidences(b, a, p, 1, 7.5)
+    assert np.array_equal(r1["counts_a"], r2["counts_b"])
+    assert np.array_equal(r1["counts_b"], r2["counts_a"]) and r1["n_pairs"] == r2["n_pairs"]
+    r3 = o.coincidences(a, a, p, 0, 0.0)
+    assert np.array_equal(r3["counts_a"], np.bincount(a["k"] // p.n_fdot, minlength=p.n_f0))
+    empty = {"tau": np.zeros(0, np.int64), "k": np.zeros(0, np.int64)}
+    r4 = o.coincidences(a, empty, p, 3, 1e9)
+    assert r4["n_pairs"] == 0 and not r4["counts_a"].any()
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -56,6 +56,16 @@ MUTANTS = {
     "tails_local_index": ("ks.append(g.k_global[k0 + j])", "ks.append(k0 + j)"),
     "tail_counts_by_fdot": ("counts += np.bincount(g.bin[k0 + j], minlength=g.n_bins)",
                             "counts += np.bincount((k0 + j) // nfd % g.n_bins, minlength=g.n_bins)[::-1]"),
+    "coinc_strict_df": ("if abs(fa[i] - fb[j]) <= df:", "if abs(fa[i] - fb[j]) < df:"),
+    "coinc_no_dtau": ("for t in range(int(ta[i]) - dtau, int(ta[i]) + dtau + 1):",
+                      "for t in range(int(ta[i]), int(ta[i]) + 1):"),
+    "coinc_one_sided_dtau": ("for t in range(int(ta[i]) - dtau, int(ta[i]) + dtau + 1):",
+                             "for t in range(int(ta[i]), int(ta[i]) + dtau + 1):"),
+    "coinc_index_as_frequency": ("fa, fb = template_f0(p, ka), template_f0(p, kb)",
+                                 "fa, fb = ka.astype(float), kb.astype(float)"),
+    "coinc_fdot_as_f0_index": ("i = np.asarray(k_global, dtype=np.int64) // p.n_fdot",
+                               "i = np.asarray(k_global, dtype=np.int64) % p.n_f0"),
+    "coinc_unsharded_bins": ("lo = int(g.k_global[0]) // p.n_fdot", "lo = 0"),
 }
 
 
