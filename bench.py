@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 METRIC = "template×offset correlations/s vs plain FP32 at stated error; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "f16x2": 2500.0}   # MI355X dense MFMA peaks
 MFMA_TERMS = {"fp32": 1, "bf16x3": 3, "f16x2": 2}                   # MFMA products per tap
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 5e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3}
 
 
 def log(*a):
@@ -119,6 +119,38 @@ def cpu_baseline(p, x64, xc64, n_off):
                  "sample": f"{offs.shape[0]} offsets of the 32 s data series (a block around "
                            f"the injection + seeded random picks) x all {K} templates, "
                            f"float64 NumPy/BLAS, {dt:.1f} s"}
+
+
+def tails_leg(bf, torch, p, xs, prec, kappa, steps):
+    """Times the search with kappa-sigma tails (two contraction passes) on the same series:
+    one untimed run, then `steps` timed runs."""
+    import numpy as np
+    bank = bf.bank_create(p, prec)
+    prm = bf.make_params()
+    ns = [int(x.shape[0]) for x in xs]
+    outs = [bf.alloc_outputs(bank, n, prm, x.device) for n, x in zip(ns, xs)]
+    tails = [bf.alloc_tails(bank, 1 << 22, x.device) for x in xs]
+    ws = torch.empty(bf.tails_workspace_bytes(bank, ns, prm), dtype=torch.uint8,
+                     device=xs[0].device)
+    bf.search_tails(bank, xs, kappa, 0, prm, outs=outs, tails=tails, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bf.search_tails(bank, xs, kappa, 0, prm, outs=outs, tails=tails, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    corr = bank.K * sum(n - p.L + 1 for n in ns)
+    n_tails = [int(t["n_tails"][0]) for t in tails]
+    counts = [t["bin_counts"].cpu().numpy().view("uint32").astype("int64") for t in tails]
+    sig = tails[0]["sigma"].cpu().numpy()
+    res = {"kappa": kappa, "precision_form": prec, "ms_per_step": wall / steps * 1e3,
+           "correlations_per_s": corr * steps / wall, "passes": 2,
+           "n_tails": n_tails, "tail_counts_total": [int(c.sum()) for c in counts],
+           "sigma_median_x_sqrtL": float(np.median(sig) * np.sqrt(p.L)),
+           "series": ["data", "control"][:len(xs)]}
+    del bank, outs, tails, ws
+    torch.cuda.empty_cache()
+    return res
 
 
 def serving_leg(bf, prec, n_segments, budget_gib, slots):
@@ -229,6 +261,8 @@ def main() -> int:
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
+    ap.add_argument("--tails-kappa", type=float, default=5.0,
+                    help="search depth of the kappa-sigma tail leg (0 skips it)")
     ap.add_argument("--extra-forms", default="f16x2",
                     help="comma-separated further precision forms to time and check ('' skips)")
     ap.add_argument("--cpu-offsets", type=int, default=1024, help="0 skips the oracle leg")
@@ -281,6 +315,12 @@ def main() -> int:
         log(f"timing {form}: 1 warmup + {args.fp32_steps} steps")
         extra[form] = time_form(bf, torch, p, xs, form, args.fp32_steps, 1)
         log(f"  {extra[form]['value']:.4g} corr/s, {extra[form]['ms_per_step']:.1f} ms/step")
+
+    tails = None
+    if args.tails_kappa > 0:
+        log(f"tails leg: kappa = {args.tails_kappa}, {args.precision}, 1 + 2 runs")
+        tails = tails_leg(bf, torch, p, xs, args.precision, args.tails_kappa, 2)
+        log(f"  {tails}")
 
     cpu = None
     err = {}
@@ -338,6 +378,7 @@ def main() -> int:
                                "tile": kernel_tile(form),
                                "roofline": roofline(r, p, form, kernel_tile(form))}
                         for form, r in extra.items()} or None,
+        "tails": tails,
         "error_vs_fp64": err or None,
         "cpu_baseline": cpu,
         "serving": serving,

@@ -67,7 +67,8 @@ typedef enum {
                     relative error (short templates) */
   BF_F16X2 = 3   /* fp16 hi+lo split of the templates, fp16 data with a power-of-two strip
                     scale; h_hi*x + h_lo*x (two MFMA products per tap).  The data's fp16
-                    rounding bounds the error: ~2e-4 relative, stated bound 5e-4 */
+                    rounding bounds the error: ~1e-4 to 7e-4 relative, stated bound
+                    1e-3 */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;
@@ -163,6 +164,70 @@ bf_status bf_search_segment(const bf_bank* bank, const float* x, int64_t n,
 bf_status bf_search_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
                           const bf_search_params* params, void* workspace,
                           size_t workspace_bytes, bf_stream stream);
+
+/* ---- kappa-sigma tails (Sec. 2.2 and the Fig. 5 caption: only correlations above kappa
+ * sigma leave the GPU; Fig. 6 caption: pseudo-spectra of their counts) -------------------
+ * sigma_k of a series = sqrt(mean over its non-degenerate offsets of rho_k(tau)^2): the
+ * spread of template k's matched-filter output (its variance, as a zero-mean template gives
+ * a zero-mean output; the paper obtains it from the spectra by Parseval's theorem, here it
+ * is summed in the contraction's epilogue).  A tail is an offset-template pair with
+ * |rho_k(tau)| > kappa * sigma_k (strict); the pseudo-spectrum counts the tails per f0 bin.
+ * Tail outputs of one series (device pointers, caller-owned):
+ *   sigma[K]        sigma_k, float32 (0 for every k if all windows are degenerate)
+ *   tau, k, rho     [capacity] offset, global template index and signed rho (float32) of
+ *                   each tail, in unspecified order; may be NULL when capacity is 0
+ *   bin_counts[B]   tails per f0 bin, all tails counted (uint32)
+ *   n_tails[1]      the number of tails (int64); when it exceeds capacity the lists hold
+ *                   `capacity` of them, which ones is unspecified
+ * The set of tails, their values, sigma and the counts are deterministic and, as for the
+ * search, identical alone or in a batch. */
+typedef struct {
+  float* sigma;
+  int32_t* tau;
+  int32_t* k;
+  float* rho;
+  uint32_t* bin_counts;
+  int64_t* n_tails;
+  int64_t capacity;
+} bf_tails;
+
+/* One series of a tail search: x and the search outputs as in bf_segment, and its tails. */
+typedef struct {
+  const float* x;
+  int64_t n;
+  bf_result out;
+  bf_tails tails;
+} bf_tail_segment;
+
+/* Device workspace bytes of a tail search (bf_workspace_bytes plus K_pad * 12 bytes and
+ * change per series). */
+bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_t n_segs,
+                                   const bf_search_params* params, size_t* bytes);
+
+/* The search of bf_search_batch plus the kappa-sigma tails of every series: the
+ * contraction runs twice on the stream (the first pass also sums rho^2 per template, the
+ * second extracts the tails against kappa * sigma_k).  kappa finite and >= 0; sigma,
+ * bin_counts and n_tails are required.  segs is a host array. */
+bf_status bf_search_tails(const bf_bank* bank, const bf_tail_segment* segs, int32_t n_segs,
+                          float kappa, const bf_search_params* params, void* workspace,
+                          size_t workspace_bytes, bf_stream stream);
+
+/* ---- Two-detector coincidence (Fig. 6 caption: pseudo-spectra of simultaneous tails in
+ * two detectors, counted with frequency pairs within a width) ----------------------------
+ * Channels a and b are two simultaneous series of the same length (n_offsets = W offsets),
+ * searched with one bank by bf_search_tails.  A tail (tau, k) of a is coincident when b has
+ * a tail (tau', k') with |tau - tau'| <= dtau and |f0(k) - f0(k')| <= df (f0 = the
+ * template's start frequency on the bank grid); likewise for b.  Outputs (device,
+ * caller-owned): counts_a[B] and counts_b[B], the coincident tails of each channel per f0
+ * bin, and n_pairs[1] (int64), the coincident pairs.  Only the listed tails count
+ * (min(n_tails, capacity) of each list); entries outside the bank share or the offsets are
+ * ignored.  dtau >= 0, df >= 0 (+inf allowed).  Asynchronous on stream. */
+bf_status bf_coincidence_workspace_bytes(const bf_bank* bank, int64_t n_offsets,
+                                         int64_t capacity_b, size_t* bytes);
+bf_status bf_coincidence(const bf_bank* bank, const bf_tails* a, const bf_tails* b,
+                         int64_t n_offsets, int32_t dtau, double df, uint32_t* counts_a,
+                         uint32_t* counts_b, int64_t* n_pairs, void* workspace,
+                         size_t workspace_bytes, bf_stream stream);
 
 /* ---- Serving: continuous batching with a device-resident bank --------------------------
  * A server owns a worker thread, `ticks_in_flight` HIP streams and one device allocation of

@@ -27,7 +27,9 @@ EXPORTED = ["bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy"
             "bf_workspace_bytes", "bf_search_segment", "bf_search_batch", "bf_plan",
             "bf_set_timing", "bf_kernel_times", "bf_last_error",
             "bf_server_create", "bf_server_request_bytes", "bf_submit", "bf_poll", "bf_fetch",
-            "bf_cancel", "bf_server_stats", "bf_server_destroy"]
+            "bf_cancel", "bf_server_stats", "bf_server_destroy",
+            "bf_tails_workspace_bytes", "bf_search_tails",
+            "bf_coincidence_workspace_bytes", "bf_coincidence"]
 STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
@@ -59,6 +61,17 @@ class Result(ctypes.Structure):
 
 class Segment(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", Result)]
+
+
+class Tails(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("k", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("bin_counts", ctypes.c_void_p),
+                ("n_tails", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class TailSegment(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", Result),
+                ("tails", Tails)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -106,6 +119,13 @@ def lib() -> ctypes.CDLL:
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
                             ctypes.POINTER(i32)],
         "bf_server_destroy": [vp],
+        "bf_tails_workspace_bytes": [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(SearchParams),
+                                     ctypes.POINTER(sz)],
+        "bf_search_tails": [vp, ctypes.POINTER(TailSegment), i32, ctypes.c_float,
+                            ctypes.POINTER(SearchParams), vp, sz, vp],
+        "bf_coincidence_workspace_bytes": [vp, i64, i64, ctypes.POINTER(sz)],
+        "bf_coincidence": [vp, ctypes.POINTER(Tails), ctypes.POINTER(Tails), i64, i32,
+                           ctypes.c_double, vp, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -276,6 +296,87 @@ def search_batch(bank: Bank, xs: list, params: SearchParams | None = None,
                                  ctypes.byref(params), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), ctypes.c_void_p(_stream(stream))))
     return outs
+
+
+def tails_workspace_bytes(bank: Bank, ns, params: SearchParams) -> int:
+    arr = (ctypes.c_int64 * len(ns))(*[int(v) for v in ns])
+    out = ctypes.c_size_t()
+    _check(lib().bf_tails_workspace_bytes(ctypes.c_void_p(bank.handle), arr, len(ns),
+                                          ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def alloc_tails(bank: Bank, capacity: int, device) -> dict:
+    """torch tensors for the tail outputs of one series."""
+    return {"sigma": torch.empty(bank.K, dtype=torch.float32,
+                                 device=device),
+            "tau": torch.empty(capacity, dtype=torch.int32, device=device),
+            "k": torch.empty(capacity, dtype=torch.int32, device=device),
+            "rho": torch.empty(capacity, dtype=torch.float32, device=device),
+            "bin_counts": torch.empty(bank.n_bins, dtype=torch.int32, device=device),  # uint32
+            "n_tails": torch.empty(1, dtype=torch.int64, device=device)}
+
+
+def search_tails(bank: Bank, xs: list, kappa: float, capacity: int,
+                 params: SearchParams | None = None, outs: list | None = None,
+                 tails: list | None = None, workspace: torch.Tensor | None = None,
+                 stream=None) -> tuple[list, list]:
+    """The batched search plus the kappa-sigma tails of each float32 device series; returns
+    (search output dicts, tail output dicts).  A series' tail lists hold min(n_tails,
+    capacity) valid entries, in unspecified order."""
+    params = params or make_params()
+    ns = [int(x.shape[0]) for x in xs]
+    for x in xs:
+        assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    outs = outs if outs is not None else [alloc_outputs(bank, n, params, x.device)
+                                          for n, x in zip(ns, xs)]
+    tails = tails if tails is not None else [alloc_tails(bank, capacity, x.device) for x in xs]
+    ws = workspace if workspace is not None else torch.empty(
+        tails_workspace_bytes(bank, ns, params), dtype=torch.uint8, device=xs[0].device)
+    segs = (TailSegment * len(xs))()
+    for i, (x, o, t) in enumerate(zip(xs, outs, tails)):
+        segs[i].x = x.data_ptr()
+        segs[i].n = ns[i]
+        segs[i].out = _result(o)
+        segs[i].tails = Tails(sigma=_ptr(t["sigma"]), tau=_ptr(t["tau"]), k=_ptr(t["k"]),
+                              rho=_ptr(t["rho"]), bin_counts=_ptr(t["bin_counts"]),
+                              n_tails=_ptr(t["n_tails"]), capacity=int(t["tau"].numel()))
+    _check(lib().bf_search_tails(ctypes.c_void_p(bank.handle), segs, len(xs),
+                                 ctypes.c_float(kappa), ctypes.byref(params),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 ctypes.c_void_p(_stream(stream))))
+    return outs, tails
+
+
+def _tails_struct(t: dict) -> Tails:
+    return Tails(sigma=_ptr(t.get("sigma")), tau=_ptr(t["tau"]), k=_ptr(t["k"]),
+                 rho=_ptr(t.get("rho")), bin_counts=_ptr(t.get("bin_counts")),
+                 n_tails=_ptr(t["n_tails"]), capacity=int(t["tau"].numel()))
+
+
+def coincidence(bank: Bank, tails_a: dict, tails_b: dict, n_offsets: int, dtau: int,
+                df: float, stream=None) -> dict:
+    """Coincident tails of two channels (tail dicts of search_tails); returns device tensors
+    counts_a, counts_b (uint32 bit patterns per f0 bin) and n_pairs."""
+    dev = tails_a["n_tails"].device
+    cap_b = int(tails_b["tau"].numel())
+    nb = ctypes.c_size_t()
+    _check(lib().bf_coincidence_workspace_bytes(ctypes.c_void_p(bank.handle), int(n_offsets),
+                                                cap_b, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    out = {"counts_a": torch.empty(bank.n_bins, dtype=torch.int32, device=dev),
+           "counts_b": torch.empty(bank.n_bins, dtype=torch.int32, device=dev),
+           "n_pairs": torch.empty(1, dtype=torch.int64, device=dev)}
+    ta, tb = _tails_struct(tails_a), _tails_struct(tails_b)
+    _check(lib().bf_coincidence(ctypes.c_void_p(bank.handle), ctypes.byref(ta),
+                                ctypes.byref(tb), int(n_offsets), int(dtau),
+                                ctypes.c_double(df), ctypes.c_void_p(out["counts_a"].data_ptr()),
+                                ctypes.c_void_p(out["counts_b"].data_ptr()),
+                                ctypes.c_void_p(out["n_pairs"].data_ptr()),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(_stream(stream))))
+    out["_workspace"] = ws    # keep alive until the stream has run
+    return out
 
 
 def set_timing(enable: bool) -> None:

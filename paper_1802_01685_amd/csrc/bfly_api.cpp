@@ -191,7 +191,7 @@ int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per C
 // wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i] (e.g. "2x8i", i = interleaved)
 // overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
 // depend on it (FP8 does, through its per-strip scales).
-void choose_tile(int precision, int32_t* tm, int32_t* tn, int32_t* pipe) {
+void choose_tile(int precision, int mode, int32_t* tm, int32_t* tn, int32_t* pipe) {
   // Defaults from measurement on MI355X: the split forms are fastest with 2 x 8 blocks and
   // the interleaved schedule; FP32 (64-cycle MFMAs) and FP8 with 2 x 4.
   const bool split = precision == BF_BF16X3 || precision == BF_F16X2;
@@ -203,7 +203,7 @@ void choose_tile(int precision, int32_t* tm, int32_t* tn, int32_t* pipe) {
   char il = 0;
   if (e && sscanf(e, "%dx%d%c", &a, &c, &il) >= 2) {
     const int pp = il == 'i' ? 1 : 0;
-    if (main_variant_exists(precision, a, c, pp)) {
+    if (main_variant_exists(precision, a, c, pp, mode)) {
       *tm = a;
       *tn = c;
       *pipe = pp;
@@ -222,9 +222,11 @@ struct TimingLog {
 };
 thread_local TimingLog t_timing;
 
+// tails: per-series tail outputs for a tail search (else null), with its kappa.
 bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
                     const bf_search_params* prm, void* workspace, size_t ws_bytes,
-                    hipStream_t stream) {
+                    hipStream_t stream, const bf_tails* tails = nullptr,
+                    float kappa = 0.0f) {
   if (!bank) return fail(BF_EINVAL, "bank is NULL");
   if (!segs || n_segs < 1) return fail(BF_EINVAL, "need at least one series");
   bf_status st = check_params(prm);
@@ -238,8 +240,11 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
       return fail(BF_EINVAL, "series %d is too long", i);
     if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
   }
+  const bool with_tails = tails != nullptr;
+  if (with_tails && !(kappa >= 0.0f && std::isfinite(kappa)))
+    return fail(BF_EINVAL, "kappa must be finite and >= 0");
   size_t need = table_bytes(n_segs);
-  for (int32_t i = 0; i < n_segs; ++i) need += series_ws_bytes(b, segs[i].n);
+  for (int32_t i = 0; i < n_segs; ++i) need += series_ws_bytes(b, segs[i].n, with_tails);
   if (!workspace) return fail(BF_EINVAL, "workspace is NULL");
   if (ws_bytes < need)
     return fail(BF_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
@@ -255,19 +260,31 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     const void* outs[6] = {o.max_abs, o.argmax, o.spec, o.spectrum, o.hist, o.n_degenerate};
     for (const void* q : outs)
       if (q && (st = check_device_ptr(q, "output buffer")) != BF_OK) return st;
+    if (with_tails) {
+      const bf_tails& t = tails[i];
+      if (!t.sigma || !t.n_tails || !t.bin_counts)
+        return fail(BF_EINVAL, "series %d: tails need sigma, bin_counts and n_tails", i);
+      if (t.capacity < 0) return fail(BF_EINVAL, "series %d: negative tail capacity", i);
+      if (t.capacity > 0 && (!t.tau || !t.k || !t.rho))
+        return fail(BF_EINVAL, "series %d: tail lists are NULL with capacity > 0", i);
+      const void* touts[6] = {t.sigma, t.n_tails, t.bin_counts, t.tau, t.k, t.rho};
+      for (const void* q : touts)
+        if (q && (st = check_device_ptr(q, "tail buffer")) != BF_OK) return st;
+    }
   }
 
-  const SearchDev sp = make_search(b, prm);
+  const SearchDev sp = make_search(b, prm, with_tails ? MODE_SIGMA : MODE_SEARCH, kappa);
   std::vector<SeriesBufs> sb((size_t)n_segs);
   char* ws = (char*)workspace;
   size_t off = table_bytes(n_segs);
   for (int32_t i = 0; i < n_segs; ++i) {
     SeriesBufs& q = sb[(size_t)i];
-    series_ws_carve(b, segs[i].n, ws + off, &q);
-    off += series_ws_bytes(b, segs[i].n);
+    series_ws_carve(b, segs[i].n, ws + off, &q, with_tails);
+    off += series_ws_bytes(b, segs[i].n, with_tails);
     q.x = segs[i].x;
     q.n = segs[i].n;
     q.out = segs[i].out;
+    if (with_tails) q.tails = &tails[i];
   }
   int slots = 0;
   if ((st = device_slots(&slots)) != BF_OK) return st;
@@ -291,14 +308,18 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   if (g_timing && (te = timing_slot(dev, &st)) == nullptr) return st;
   const int32_t xb =
       (int32_t)std::min<int64_t>(std::max<int64_t>((ti.max_words + 255) / 256, 1), 2048);
-  return enqueue_kernels(b, sp, tab_dev, n_segs, xb, ti.n_items, stream, te);
+  if (!with_tails) return enqueue_kernels(b, sp, tab_dev, n_segs, xb, ti.n_items, stream, te);
+  SearchDev sp_t = sp;
+  sp_t.mode = MODE_TAILS;
+  HIP_TRY(prepare_main(b, sp_t), "hipFuncSetAttribute(k_main)");
+  return enqueue_tail_kernels(b, sp, sp_t, tab_dev, n_segs, xb, ti.n_items, stream, te);
 }
 
 }  // namespace
 
 namespace bfly {
 
-size_t series_ws_bytes(const BankDev& b, int64_t n) {
+size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails) {
   const int64_t W = n - b.L + 1;
   size_t off = 0;
   off = align256(off + (size_t)(n + 1) * 4 * sizeof(double));
@@ -306,10 +327,15 @@ size_t series_ws_bytes(const BankDev& b, int64_t n) {
   off = align256(off + (size_t)W * sizeof(double));
   off = align256(off + (size_t)W * sizeof(unsigned long long));
   off = align256(off + (size_t)b.n_bins * sizeof(unsigned long long));
+  if (tails) {
+    off = align256(off + (size_t)b.K_pad * sizeof(unsigned long long));
+    off = align256(off + sizeof(unsigned long long));
+    off = align256(off + (size_t)b.K_pad * sizeof(float));
+  }
   return off;
 }
 
-void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s) {
+void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s, bool tails) {
   const int64_t W = n - b.L + 1;
   size_t off = 0;
   s->pre = (double*)(base + off);
@@ -321,6 +347,14 @@ void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s) {
   s->mkey = (unsigned long long*)(base + off);
   off = align256(off + (size_t)W * sizeof(unsigned long long));
   s->spec_acc = (unsigned long long*)(base + off);
+  off = align256(off + (size_t)b.n_bins * sizeof(unsigned long long));
+  if (tails) {
+    s->sig_acc = (unsigned long long*)(base + off);
+    off = align256(off + (size_t)b.K_pad * sizeof(unsigned long long));
+    s->n_ok = (unsigned long long*)(base + off);
+    off = align256(off + sizeof(unsigned long long));
+    s->thr = (float*)(base + off);
+  }
 }
 
 bf_status check_params(const bf_search_params* p) {
@@ -336,14 +370,16 @@ bf_status check_params(const bf_search_params* p) {
   return BF_OK;
 }
 
-SearchDev make_search(const BankDev& b, const bf_search_params* prm) {
+SearchDev make_search(const BankDev& b, const bf_search_params* prm, int mode, float kappa) {
   SearchDev sp;
+  sp.mode = mode;
+  sp.kappa = kappa;
   sp.norm = prm->norm;
   sp.t_block = prm->t_block;
   sp.hist_bins = prm->hist_bins;
   sp.hist_lo = prm->hist_lo;
   sp.hist_hi = prm->hist_hi;
-  choose_tile(b.precision, &sp.tm, &sp.tn, &sp.pipe);
+  choose_tile(b.precision, mode, &sp.tm, &sp.tn, &sp.pipe);
   sp.n_wg = 32 * sp.tn * WG_WAVES;
   return sp;
 }
@@ -415,6 +451,17 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
     d.hist = s[i].out.hist;
     d.n_degenerate = s[i].out.n_degenerate;
     d.spec_rows = (d.W + sp.t_block - 1) / sp.t_block;
+    const bf_tails* t = s[i].tails;
+    d.sig_acc = t ? s[i].sig_acc : nullptr;
+    d.n_ok = t ? s[i].n_ok : nullptr;
+    d.thr = t ? s[i].thr : nullptr;
+    d.sigma = t ? t->sigma : nullptr;
+    d.t_tau = t ? t->tau : nullptr;
+    d.t_k = t ? t->k : nullptr;
+    d.t_rho = t ? t->rho : nullptr;
+    d.t_bins = t ? t->bin_counts : nullptr;
+    d.n_tails = t ? (unsigned long long*)t->n_tails : nullptr;
+    d.tail_cap = t ? t->capacity : 0;
     ti.max_W = std::max(ti.max_W, d.W);
     ti.max_words = std::max(ti.max_words, std::max(d.W, d.spec ? d.spec_rows * b.n_bins : 0));
   }
@@ -468,6 +515,18 @@ bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr*
   if (te) HIP_TRY(hipEventRecord(te->ev[4], stream), "hipEventRecord");
   HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp, stream), "k_finalize launch");
   if (te) HIP_TRY(hipEventRecord(te->ev[5], stream), "hipEventRecord");
+  return BF_OK;
+}
+
+bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
+                               const SearchDev& sp_tails, const BatchHdr* table_dev,
+                               int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                               hipStream_t stream, TimingSet* te) {
+  bf_status st = enqueue_kernels(b, sp_sigma, table_dev, seg_slots, x_blocks, main_blocks,
+                                 stream, te);
+  if (st != BF_OK) return st;
+  HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
+  HIP_TRY(launch_main(table_dev, main_blocks, b, sp_tails, stream), "k_main launch");
   return BF_OK;
 }
 
@@ -603,6 +662,122 @@ bf_status bf_search_batch(const bf_bank* bank, const bf_segment* segs, int32_t n
   }
 }
 
+bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_t n_segs,
+                                   const bf_search_params* params, size_t* bytes) {
+  try {
+    if (!bank) return fail(BF_EINVAL, "bank is NULL");
+    if (!n || n_segs < 1) return fail(BF_EINVAL, "need at least one series length");
+    if (!bytes) return fail(BF_EINVAL, "bytes is NULL");
+    bf_status st = check_params(params);
+    if (st != BF_OK) return st;
+    for (int32_t i = 0; i < n_segs; ++i)
+      if (n[i] < bank->dev.L)
+        return fail(BF_EINVAL, "series %d has %lld samples, fewer than L = %d", i,
+                    (long long)n[i], bank->dev.L);
+    size_t total = table_bytes(n_segs);
+    for (int32_t i = 0; i < n_segs; ++i) total += series_ws_bytes(bank->dev, n[i], true);
+    *bytes = total;
+    return BF_OK;
+  } catch (...) {
+    return fail(BF_ENOMEM, "internal error");
+  }
+}
+
+bf_status bf_search_tails(const bf_bank* bank, const bf_tail_segment* segs, int32_t n_segs,
+                          float kappa, const bf_search_params* params, void* workspace,
+                          size_t workspace_bytes, bf_stream stream) {
+  try {
+    if (!segs || n_segs < 1) return fail(BF_EINVAL, "need at least one series");
+    std::vector<bf_segment> ss((size_t)n_segs);
+    std::vector<bf_tails> tt((size_t)n_segs);
+    for (int32_t i = 0; i < n_segs; ++i) {
+      ss[(size_t)i].x = segs[i].x;
+      ss[(size_t)i].n = segs[i].n;
+      ss[(size_t)i].out = segs[i].out;
+      tt[(size_t)i] = segs[i].tails;
+    }
+    return run_batch(bank, ss.data(), n_segs, params, workspace, workspace_bytes,
+                     (hipStream_t)stream, tt.data(), kappa);
+  } catch (...) {
+    return fail(BF_ENOMEM, "internal error");
+  }
+}
+
+namespace {
+size_t coinc_ws_bytes(int64_t W, int64_t cap_b) {
+  return align256((size_t)(W + 1) * 4) + align256((size_t)W * 4) +
+         2 * align256((size_t)cap_b * 4) + 256;
+}
+}  // namespace
+
+bf_status bf_coincidence_workspace_bytes(const bf_bank* bank, int64_t n_offsets,
+                                         int64_t capacity_b, size_t* bytes) {
+  if (!bank || !bytes) return fail(BF_EINVAL, "bank or bytes is NULL");
+  if (n_offsets < 1 || n_offsets > ((int64_t)1 << 31) - 2)
+    return fail(BF_EINVAL, "n_offsets must be in [1, 2^31 - 2]");
+  if (capacity_b < 0 || capacity_b > ((int64_t)1 << 32) - 1)
+    return fail(BF_EINVAL, "capacity_b must be in [0, 2^32 - 1]");
+  *bytes = coinc_ws_bytes(n_offsets, capacity_b);
+  return BF_OK;
+}
+
+bf_status bf_coincidence(const bf_bank* bank, const bf_tails* a, const bf_tails* b,
+                         int64_t n_offsets, int32_t dtau, double df, uint32_t* counts_a,
+                         uint32_t* counts_b, int64_t* n_pairs, void* workspace,
+                         size_t workspace_bytes, bf_stream stream) {
+  try {
+    if (!bank || !a || !b) return fail(BF_EINVAL, "bank or tails is NULL");
+    if (n_offsets < 1 || n_offsets > ((int64_t)1 << 31) - 2)
+      return fail(BF_EINVAL, "n_offsets must be in [1, 2^31 - 2]");
+    if (dtau < 0) return fail(BF_EINVAL, "dtau must be >= 0");
+    if (!(df >= 0.0)) return fail(BF_EINVAL, "df must be >= 0");
+    if (!counts_a || !counts_b || !n_pairs) return fail(BF_EINVAL, "an output is NULL");
+    const bf_tails* sides[2] = {a, b};
+    for (const bf_tails* t : sides) {
+      if (!t->n_tails) return fail(BF_EINVAL, "tails need n_tails");
+      if (t->capacity < 0 || t->capacity > ((int64_t)1 << 32) - 1)
+        return fail(BF_EINVAL, "tail capacity must be in [0, 2^32 - 1]");
+      if (t->capacity > 0 && (!t->tau || !t->k))
+        return fail(BF_EINVAL, "tail lists are NULL with capacity > 0");
+    }
+    const size_t need = coinc_ws_bytes(n_offsets, b->capacity);
+    if (!workspace) return fail(BF_EINVAL, "workspace is NULL");
+    if (workspace_bytes < need)
+      return fail(BF_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+    if (((uintptr_t)workspace & 255) != 0)
+      return fail(BF_EINVAL, "workspace not 256-byte aligned");
+    bf_status st;
+    const void* ptrs[8] = {workspace, counts_a, counts_b, n_pairs, a->n_tails, b->n_tails,
+                           a->tau, b->tau};
+    for (const void* q : ptrs)
+      if (q && (st = check_device_ptr(q, "coincidence buffer")) != BF_OK) return st;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != bank->device)
+      return fail(BF_EINVAL, "bank lives on device %d, current is %d", bank->device, dev);
+    char* ws = (char*)workspace;
+    CoincWork w;
+    size_t off = 0;
+    w.start = (uint32_t*)(ws + off);
+    off += align256((size_t)(n_offsets + 1) * 4);
+    w.cursor = (uint32_t*)(ws + off);
+    off += align256((size_t)n_offsets * 4);
+    w.order = (uint32_t*)(ws + off);
+    off += align256((size_t)b->capacity * 4);
+    w.flag_b = (uint32_t*)(ws + off);
+    off += align256((size_t)b->capacity * 4);
+    w.n_pairs = (unsigned long long*)n_pairs;
+    const CoincSide sa = {a->tau, a->k, a->n_tails, a->capacity, counts_a};
+    const CoincSide sb = {b->tau, b->k, b->n_tails, b->capacity, counts_b};
+    HIP_TRY(launch_coincidence(sa, sb, w, bank->grid, bank->dev.n_bins, bank->dev.n_fdot,
+                               n_offsets, dtau, df, (hipStream_t)stream),
+            "coincidence launch");
+    return BF_OK;
+  } catch (...) {
+    return fail(BF_ENOMEM, "internal error");
+  }
+}
+
 bf_status bf_set_timing(int32_t enable) {
   g_timing = enable != 0;
   return BF_OK;
@@ -634,7 +809,7 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   for (int32_t i = 0; i < n_segs; ++i) {
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
     int32_t tm = 0, tn = 0, pp = 0;
-    choose_tile(bank->dev.precision, &tm, &tn, &pp);
+    choose_tile(bank->dev.precision, MODE_SEARCH, &tm, &tn, &pp);
     const int64_t n_wg = 32 * (int64_t)tn * WG_WAVES;
     tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
   }
@@ -642,7 +817,7 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   bf_status st = device_slots(&slots);
   if (st != BF_OK) return st;
   int32_t tm = 0, tn = 0, pp = 0;
-  choose_tile(bank->dev.precision, &tm, &tn, &pp);
+  choose_tile(bank->dev.precision, MODE_SEARCH, &tm, &tn, &pp);
   const int32_t r = plan_ranges(bank->dev, tiles, slots, tm);
   if (n_ranges) *n_ranges = r;
   if (n_items) *n_items = tiles * r;

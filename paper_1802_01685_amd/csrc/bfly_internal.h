@@ -22,6 +22,7 @@ constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG +
 constexpr int MAX_L = 8192;
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
+constexpr double SIGMA_FIX_SCALE = 68719476736.0;   // 2^36: fixed-point sums of rho^2
 
 enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3 };
 
@@ -50,6 +51,17 @@ struct SegDesc {
   uint32_t* hist;
   int64_t* n_degenerate;
   int64_t spec_rows;    // ceil(W / t_block)
+  // kappa-sigma tails (null unless the search extracts them)
+  unsigned long long* sig_acc;   // [K_pad] fixed-point sums of rho^2 per template
+  unsigned long long* n_ok;      // [1] non-degenerate offsets
+  float* thr;                    // [K_pad] kappa * sigma_k (+inf past K)
+  float* sigma;                  // [K] output sigma_k
+  int32_t* t_tau;                // [tail_cap] tail offsets
+  int32_t* t_k;                  // [tail_cap] tail global template indices
+  float* t_rho;                  // [tail_cap] tail rho (signed)
+  uint32_t* t_bins;              // [n_bins] tails per f0 bin
+  unsigned long long* n_tails;   // [1] tails found
+  int64_t tail_cap;
 };
 
 // Header of a batch table in device memory: the table is [BatchHdr][SegDesc x n_segs].  The
@@ -98,8 +110,14 @@ struct SearchDev {
   int32_t tn;           // 32-offset blocks per wave (4 or 8)
   int32_t pipe;         // K-loop schedule: 0 blocked, 1 MFMA/load interleaved
   int32_t n_wg;         // offsets per work item = 4 * 32 * tn
+  int32_t mode;         // contraction pass: MODE_SEARCH, MODE_SIGMA or MODE_TAILS
+  float kappa;          // tails: search depth
   double hist_lo, hist_hi;
 };
+
+// Contraction passes: the search; the search that also sums rho^2 per template; the pass
+// that extracts the tails above kappa * sigma_k (and does nothing else).
+enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2 };
 
 // Bytes of the quantised templates, of the FP8 exponents, and of the whole bank allocation
 // (templates, exponents, then a 256-byte status word).
@@ -126,11 +144,35 @@ hipError_t launch_prefix(const BatchHdr* hdr, int32_t seg_slots, hipStream_t s);
 hipError_t launch_norms(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks, int L,
                         int norm, hipStream_t s);
 hipError_t prepare_main(const BankDev& b, const SearchDev& p);
-bool main_variant_exists(int precision, int tm, int tn, int pipe);
+bool main_variant_exists(int precision, int tm, int tn, int pipe, int mode);
 hipError_t launch_main(const BatchHdr* hdr, int64_t main_blocks, const BankDev& b,
                        const SearchDev& p, hipStream_t s);
 hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
                            const BankDev& b, const SearchDev& p, hipStream_t s);
+// sigma_k = sqrt(sum rho^2 / n_ok) and the tail thresholds kappa * sigma_k (MODE_SIGMA's sums
+// and k_finalize's n_ok must be complete).
+hipError_t launch_sigma(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                        const SearchDev& p, hipStream_t s);
 size_t main_lds_bytes(int precision, int L_pad, int n_wg);
+
+// Two-detector coincidence (bfly_coinc.hip).  A channel's tail list (device) and its output
+// counts per f0 bin; the workspace of the offset buckets of channel B.
+struct CoincSide {
+  const int32_t* tau;
+  const int32_t* k;
+  const int64_t* n_tails;
+  int64_t capacity;
+  uint32_t* counts;
+};
+struct CoincWork {
+  uint32_t* start;     // [W + 1] first bucket slot per offset
+  uint32_t* cursor;    // [W] scatter cursors
+  uint32_t* order;     // [capacity_b] B tail indices by offset
+  uint32_t* flag_b;    // [capacity_b] B tail has a partner
+  unsigned long long* n_pairs;
+};
+hipError_t launch_coincidence(const CoincSide& a, const CoincSide& b, const CoincWork& w,
+                              const GridDev& g, int32_t n_bins, int32_t n_fdot, int64_t W,
+                              int32_t dtau, double df, hipStream_t s);
 
 }  // namespace bfly

@@ -216,6 +216,14 @@ __global__ __launch_bounds__(256) void k_zero(const BatchHdr* __restrict__ hdr, 
   if (sg.hist)
     for (int64_t i = t0; i < p.hist_bins; i += stride) sg.hist[i] = 0u;
   if (sg.n_degenerate && t0 == 0) sg.n_degenerate[0] = 0;
+  if (sg.sig_acc) {
+    for (int64_t i = t0; i < b.K_pad; i += stride) sg.sig_acc[i] = 0ull;
+    for (int64_t i = t0; i < b.n_bins; i += stride) sg.t_bins[i] = 0u;
+    if (t0 == 0) {
+      sg.n_ok[0] = 0ull;
+      sg.n_tails[0] = 0ull;
+    }
+  }
 }
 
 hipError_t launch_zero(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
@@ -594,8 +602,9 @@ __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
   if (lane == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
 }
 
-// One work item: strip fill, template sweep, flushes.  PIPE selects the K-loop schedule.
-template <int PREC, int MB, int NB, int PIPE>
+// One work item: strip fill, template sweep, flushes.  PIPE selects the K-loop schedule,
+// MODE the pass (MainMode).
+template <int PREC, int MB, int NB, int PIPE, int MODE>
 __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int64_t item,
                                           const BankDev& b, const SearchDev& p, char* lds) {
   const SegDesc* segs = hdr_segs(hdr);
@@ -888,6 +897,36 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     const int64_t kbase = kt * (32 * MB);
     const int r_lo = (int)((k_lo > kbase ? k_lo : kbase) - kbase);        // rows owned
     const int r_hi = (int)((k_hi < kbase + (32 * MB) ? k_hi : kbase + (32 * MB)) - kbase);
+    if constexpr (MODE == MODE_TAILS) {
+      // rho = d / sqrt(E) exactly as the butterfly output is formed; every owned (tau, k)
+      // with |rho| > kappa * sigma_k is appended to the series' list and counted in its bin.
+      const float* th = sg.thr + kbase + 4 * h;
+#pragma unroll
+      for (int t = 0; t < MB; ++t)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float4 t4 = *(const float4*)(th + 32 * t + 8 * g);
+          const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = 32 * t + 8 * g + 4 * h + i;
+              const float rf = (float)((double)(acc[t][j][4 * g + i] * dscale) * inv[j]);
+              if (fabsf(rf) > tv[i] && row >= r_lo && row < r_hi) {
+                const int64_t kl = kbase + row;
+                const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
+                if ((int64_t)slot < sg.tail_cap) {
+                  sg.t_tau[slot] = (int32_t)(tau_w0 + 32 * j + n);
+                  sg.t_k[slot] = (int32_t)(b.k_offset + kl);
+                  sg.t_rho[slot] = rf;
+                }
+                atomicAdd(sg.t_bins + kl / nfd, 1u);
+              }
+            }
+        }
+      continue;
+    }
     const int bA = (int)((kbase + r_lo) / nfd), bB = (int)((kbase + r_hi - 1) / nfd);
     if (r_lo == 0 && r_hi == (32 * MB) && bA == bB) {
       // whole tile owned and inside one bin
@@ -953,6 +992,42 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
             }
       }
     }
+    if constexpr (MODE == MODE_SIGMA) {
+      // Sum of rho^2 over this wave's offsets for each owned row: per lane over its NB
+      // columns, then across the 32 lanes of each half by a transposing butterfly (after
+      // the step of width w a lane keeps the half of its partial sums selected by lane
+      // bit w), so lane n of a half ends with the sum for slot n = 16t + 4g + i4.  The sums
+      // are added to the per-template fixed-point totals, exact and order-independent.
+      static_assert(MB == 2, "the sigma pass is compiled for two template blocks");
+      float q[32];
+#pragma unroll
+      for (int v = 0; v < 32; ++v) q[v] = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < MB; ++t)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float rf = (float)((double)(acc[t][j][v] * dscale) * inv[j]);
+            q[16 * t + v] = fmaf(rf, rf, q[16 * t + v]);
+          }
+#pragma unroll
+      for (int w = 16; w >= 1; w >>= 1) {
+        const bool up = (n & w) != 0;
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+          const float keep = up ? q[w + i] : q[i];
+          const float give = up ? q[i] : q[w + i];
+          q[i] = keep + __shfl_xor(give, w, 64);
+        }
+      }
+      const int row = 32 * (n >> 4) + 8 * ((n & 15) >> 2) + 4 * h + (n & 3);
+      if (row >= r_lo && row < r_hi) {
+        const unsigned long long f =
+            (unsigned long long)__double2ll_rn((double)q[0] * SIGMA_FIX_SCALE);
+        if (f) atomicAdd(sg.sig_acc + kbase + row, f);
+      }
+    }
   }
   if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
 
@@ -978,60 +1053,80 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 // Each work-group runs items blockIdx.x, blockIdx.x + gridDim.x, ...: one item per
 // work-group for a plain batch launch, a persistent loop for captured launches whose grid
 // is fixed while the batch changes.
-template <int PREC, int MB, int NB, int PIPE>
+template <int PREC, int MB, int NB, int PIPE, int MODE>
 __global__ __launch_bounds__(WG_THREADS, 1) void k_main(const BatchHdr* __restrict__ hdr,
                                                         BankDev b, SearchDev p) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int64_t n_items = hdr->n_items;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    main_item<PREC, MB, NB, PIPE>(hdr, item, b, p, lds);
+    main_item<PREC, MB, NB, PIPE, MODE>(hdr, item, b, p, lds);
     __syncthreads();   // the next item refills the strip
   }
 }
 
-template <int PREC, int MB, int NB, int PIPE>
+template <int PREC, int MB, int NB, int PIPE, int MODE>
 static hipError_t prepare_main_t(const BankDev& b) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  return hipFuncSetAttribute((const void*)k_main<PREC, MB, NB, PIPE>,
+  return hipFuncSetAttribute((const void*)k_main<PREC, MB, NB, PIPE, MODE>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int PREC, int MB, int NB, int PIPE>
+template <int PREC, int MB, int NB, int PIPE, int MODE>
 static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                 const SearchDev& p, hipStream_t s) {
   const size_t lds = main_lds_bytes(PREC, b.L_pad, 32 * NB * WG_WAVES);
-  hipLaunchKernelGGL((k_main<PREC, MB, NB, PIPE>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
+  hipLaunchKernelGGL((k_main<PREC, MB, NB, PIPE, MODE>), dim3((unsigned)blocks), dim3(WG_THREADS), lds, s,
                      hdr, b, p);
   return hipGetLastError();
 }
 
-// The compiled kernel variants: (template blocks, offset blocks per wave, K-loop schedule).
+// The compiled kernel variants: (template blocks, offset blocks per wave, K-loop schedule)
+// for the search; the two passes of the tail search exist for each precision's default
+// shape only (2 x 8 interleaved for the split forms, 2 x 4 otherwise).
 #define BFLY_DISPATCH(FN, ...)                                                         \
   do {                                                                                 \
     const int v_ = p.pipe * 256 + p.tm * 16 + p.tn;                                    \
+    if (p.mode != MODE_SEARCH) {                                                       \
+      const bool m1_ = p.mode == MODE_SIGMA;                                           \
+      if (b.precision == P_FP32 && v_ == 0x024)                                        \
+        return m1_ ? FN<P_FP32, 2, 4, 0, MODE_SIGMA>(__VA_ARGS__)                      \
+                   : FN<P_FP32, 2, 4, 0, MODE_TAILS>(__VA_ARGS__);                     \
+      if (b.precision == P_BF16X3 && v_ == 0x128)                                      \
+        return m1_ ? FN<P_BF16X3, 2, 8, 1, MODE_SIGMA>(__VA_ARGS__)                    \
+                   : FN<P_BF16X3, 2, 8, 1, MODE_TAILS>(__VA_ARGS__);                   \
+      if (b.precision == P_F16X2 && v_ == 0x128)                                       \
+        return m1_ ? FN<P_F16X2, 2, 8, 1, MODE_SIGMA>(__VA_ARGS__)                     \
+                   : FN<P_F16X2, 2, 8, 1, MODE_TAILS>(__VA_ARGS__);                    \
+      if (b.precision == P_FP8 && v_ == 0x024)                                         \
+        return m1_ ? FN<P_FP8, 2, 4, 0, MODE_SIGMA>(__VA_ARGS__)                       \
+                   : FN<P_FP8, 2, 4, 0, MODE_TAILS>(__VA_ARGS__);                      \
+      return hipErrorInvalidValue;                                                     \
+    }                                                                                  \
     if (b.precision == P_FP32) {                                                       \
-      if (v_ == 0x024) return FN<P_FP32, 2, 4, 0>(__VA_ARGS__);                        \
-      if (v_ == 0x018) return FN<P_FP32, 1, 8, 0>(__VA_ARGS__);                        \
+      if (v_ == 0x024) return FN<P_FP32, 2, 4, 0, MODE_SEARCH>(__VA_ARGS__);           \
+      if (v_ == 0x018) return FN<P_FP32, 1, 8, 0, MODE_SEARCH>(__VA_ARGS__);           \
     } else if (b.precision == P_BF16X3) {                                              \
-      if (v_ == 0x024) return FN<P_BF16X3, 2, 4, 0>(__VA_ARGS__);                      \
-      if (v_ == 0x018) return FN<P_BF16X3, 1, 8, 0>(__VA_ARGS__);                      \
-      if (v_ == 0x028) return FN<P_BF16X3, 2, 8, 0>(__VA_ARGS__);                      \
-      if (v_ == 0x124) return FN<P_BF16X3, 2, 4, 1>(__VA_ARGS__);                      \
-      if (v_ == 0x128) return FN<P_BF16X3, 2, 8, 1>(__VA_ARGS__);                      \
+      if (v_ == 0x024) return FN<P_BF16X3, 2, 4, 0, MODE_SEARCH>(__VA_ARGS__);         \
+      if (v_ == 0x018) return FN<P_BF16X3, 1, 8, 0, MODE_SEARCH>(__VA_ARGS__);         \
+      if (v_ == 0x028) return FN<P_BF16X3, 2, 8, 0, MODE_SEARCH>(__VA_ARGS__);         \
+      if (v_ == 0x124) return FN<P_BF16X3, 2, 4, 1, MODE_SEARCH>(__VA_ARGS__);         \
+      if (v_ == 0x128) return FN<P_BF16X3, 2, 8, 1, MODE_SEARCH>(__VA_ARGS__);         \
     } else if (b.precision == P_F16X2) {                                               \
-      if (v_ == 0x024) return FN<P_F16X2, 2, 4, 0>(__VA_ARGS__);                       \
-      if (v_ == 0x028) return FN<P_F16X2, 2, 8, 0>(__VA_ARGS__);                       \
-      if (v_ == 0x128) return FN<P_F16X2, 2, 8, 1>(__VA_ARGS__);                       \
+      if (v_ == 0x024) return FN<P_F16X2, 2, 4, 0, MODE_SEARCH>(__VA_ARGS__);          \
+      if (v_ == 0x028) return FN<P_F16X2, 2, 8, 0, MODE_SEARCH>(__VA_ARGS__);          \
+      if (v_ == 0x128) return FN<P_F16X2, 2, 8, 1, MODE_SEARCH>(__VA_ARGS__);          \
     } else if (b.precision == P_FP8) {                                                 \
-      if (v_ == 0x024) return FN<P_FP8, 2, 4, 0>(__VA_ARGS__);                         \
-      if (v_ == 0x018) return FN<P_FP8, 1, 8, 0>(__VA_ARGS__);                         \
-      if (v_ == 0x128) return FN<P_FP8, 2, 8, 1>(__VA_ARGS__);                         \
+      if (v_ == 0x024) return FN<P_FP8, 2, 4, 0, MODE_SEARCH>(__VA_ARGS__);            \
+      if (v_ == 0x018) return FN<P_FP8, 1, 8, 0, MODE_SEARCH>(__VA_ARGS__);            \
+      if (v_ == 0x128) return FN<P_FP8, 2, 8, 1, MODE_SEARCH>(__VA_ARGS__);            \
     }                                                                                  \
     return hipErrorInvalidValue;                                                       \
   } while (0)
 
-bool main_variant_exists(int precision, int tm, int tn, int pipe) {
+bool main_variant_exists(int precision, int tm, int tn, int pipe, int mode) {
   const int v = pipe * 256 + tm * 16 + tn;
+  if (mode != MODE_SEARCH)
+    return v == ((precision == P_BF16X3 || precision == P_F16X2) ? 0x128 : 0x024);
   if (precision == P_BF16X3)
     return v == 0x024 || v == 0x018 || v == 0x028 || v == 0x124 || v == 0x128;
   if (precision == P_FP8) return v == 0x024 || v == 0x018 || v == 0x128;
@@ -1060,13 +1155,13 @@ __global__ __launch_bounds__(256) void k_finalize(const BatchHdr* __restrict__ h
   if ((int)blockIdx.y >= hdr->n_segs) return;
   const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
   __shared__ unsigned int hl[MAX_HIST_BINS];
-  __shared__ unsigned int ndeg;
+  __shared__ unsigned int ndeg, nok;
   const int tid = threadIdx.x;
   for (int i = tid; i < p.hist_bins; i += 256) hl[i] = 0u;
-  if (tid == 0) ndeg = 0u;
+  if (tid == 0) ndeg = nok = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  unsigned int my_deg = 0u;
+  unsigned int my_deg = 0u, my_ok = 0u;
   const double span = p.hist_hi - p.hist_lo;
   for (int64_t tau = (int64_t)blockIdx.x * blockDim.x + tid; tau < sg.W; tau += stride) {
     const double inv = sg.inv_norm[tau];
@@ -1081,6 +1176,7 @@ __global__ __launch_bounds__(256) void k_finalize(const BatchHdr* __restrict__ h
       q = q > 0.0 ? q : 0.0;  // also maps NaN to bin 0
       q = q > (double)(p.hist_bins - 1) ? (double)(p.hist_bins - 1) : q;
       atomicAdd(&hl[(int)q], 1u);
+      ++my_ok;
     } else {
       if (sg.max_abs) sg.max_abs[tau] = 0.0f;
       if (sg.argmax) sg.argmax[tau] = -1;
@@ -1088,7 +1184,9 @@ __global__ __launch_bounds__(256) void k_finalize(const BatchHdr* __restrict__ h
     }
   }
   if (my_deg) atomicAdd(&ndeg, my_deg);
+  if (my_ok) atomicAdd(&nok, my_ok);
   __syncthreads();
+  if (tid == 0 && sg.n_ok && nok) atomicAdd(sg.n_ok, (unsigned long long)nok);
   if (sg.hist)
     for (int i = tid; i < p.hist_bins; i += 256)
       if (hl[i]) atomicAdd(sg.hist + i, hl[i]);
@@ -1103,6 +1201,36 @@ hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blo
                            const BankDev& b, const SearchDev& p, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)x_blocks, (unsigned)seg_slots), dim3(256), 0, s,
                      hdr, b, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// sigma_k = sqrt(sum_tau rho_k^2 / n_ok) from the fixed-point sums of the sigma pass, and the
+// tail threshold kappa * sigma_k (float32, as the tails pass compares float32 rho); +inf for
+// padding templates and for a series without a non-degenerate offset.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sigma(const BatchHdr* __restrict__ hdr, BankDev b,
+                                               SearchDev p) {
+  if ((int)blockIdx.y >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
+  const double nok = (double)sg.n_ok[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b.K_pad; k += stride) {
+    float thr = __builtin_inff();
+    if (k < b.K) {
+      const double sd = nok > 0.0 ? sqrt((double)sg.sig_acc[k] / SIGMA_FIX_SCALE / nok) : 0.0;
+      if (sg.sigma) sg.sigma[k] = (float)sd;
+      if (nok > 0.0) thr = (float)((double)p.kappa * sd);
+    }
+    sg.thr[k] = thr;
+  }
+}
+
+hipError_t launch_sigma(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                        const SearchDev& p, hipStream_t s) {
+  const int64_t xb = (b.K_pad + 255) / 256;
+  hipLaunchKernelGGL(k_sigma, dim3((unsigned)(xb < 1024 ? xb : 1024), (unsigned)seg_slots),
+                     dim3(256), 0, s, hdr, b, p);
   return hipGetLastError();
 }
 

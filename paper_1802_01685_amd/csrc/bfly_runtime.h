@@ -34,19 +34,27 @@ struct SeriesBufs {
   unsigned long long* mkey;
   unsigned long long* spec_acc;
   bf_result out;
+  // tail search only (else null): workspace sums, counts, thresholds, and the outputs
+  unsigned long long* sig_acc = nullptr;
+  unsigned long long* n_ok = nullptr;
+  float* thr = nullptr;
+  const bf_tails* tails = nullptr;
 };
 
-// Bytes of one series' workspace part (prefix sums, counts, norms, maxima, spectrum sums).
-size_t series_ws_bytes(const BankDev& b, int64_t n);
+// Bytes of one series' workspace part (prefix sums, counts, norms, maxima, spectrum sums;
+// with tails also the per-template rho^2 sums and thresholds).
+size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails = false);
 // Assigns the workspace pointers of a series whose workspace part starts at base.
-void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s);
+void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s,
+                     bool tails = false);
 // Bytes of a batch table for n_segs series ([BatchHdr][SegDesc x n_segs], 256-aligned).
 inline size_t table_bytes(int32_t n_segs) {
   return align256(sizeof(BatchHdr) + (size_t)n_segs * sizeof(SegDesc));
 }
 
 bf_status check_params(const bf_search_params* p);
-SearchDev make_search(const BankDev& b, const bf_search_params* p);
+SearchDev make_search(const BankDev& b, const bf_search_params* p, int mode = MODE_SEARCH,
+                      float kappa = 0.0f);
 bf_status device_slots(int* slots);
 int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots, int tm);
 
@@ -71,5 +79,11 @@ TimingSet* timing_slot(int device, bf_status* st);
 bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr* table_dev,
                           int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
                           hipStream_t stream, TimingSet* te);
+// The tail search: the kernels above with the contraction in MODE_SIGMA, then k_sigma and
+// the MODE_TAILS contraction (sp_sigma and sp_tails differ only in mode).
+bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
+                               const SearchDev& sp_tails, const BatchHdr* table_dev,
+                               int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                               hipStream_t stream, TimingSet* te);
 
 }  // namespace bfly
