@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 METRIC = "template×offset correlations/s vs plain FP32 at stated error; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "f16x2": 2500.0}   # MI355X dense MFMA peaks
 MFMA_TERMS = {"fp32": 1, "bf16x3": 3, "f16x2": 2}                   # MFMA products per tap
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fft": 1e-5}
 
 
 def log(*a):
@@ -76,6 +76,7 @@ def time_form(bf, torch, p, xs, prec, steps, warmup):
         "corr_per_step": corr,
         "value": corr * steps / wall,
         "kernel_ms": {k: v / n_timed for k, v in kt.items()},
+        "K": K, "W": W,
         "n_ranges": n_ranges, "n_items": n_items,
         "outs": [{k: v.cpu().numpy() for k, v in o.items()} for o in outs],
     }
@@ -84,7 +85,27 @@ def time_form(bf, torch, p, xs, prec, steps, warmup):
     return res
 
 
+def fft_roofline(res, p, bf):
+    """The FFT form's fused kernel against the float32 vector peak: per (template, block) a
+    complex inverse FFT of M = N/2 points (5 M log2 M flop) plus the spectrum product and
+    real-FFT post-processing (~16 M flop)."""
+    import math
+    ms = res["kernel_ms"]["main"]
+    m = 512
+    while 2 * m < 2 * p.L:
+        m *= 2
+    valid = 2 * m - p.L + 1
+    blocks = sum(-(-w // valid) for w in res["W"])
+    flops = res["K"] * blocks * (5.0 * m * math.log2(m) + 16.0 * m)
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": 157.3, "unit": "TFLOP/s",
+            "frac": round(achieved / 157.3, 4), "traffic": None, "kernel": "k_fft_data+k_fft_main",
+            "kernel_ms": round(ms, 3), "fft_points": 2 * m, "valid_per_block": valid}
+
+
 def roofline(res, p, prec, tile):
+    if prec == "fft":
+        return fft_roofline(res, p, None)
     ms = res["kernel_ms"]["main"]
     flops = 2.0 * p.L * res["corr_per_step"]           # algorithmic: one multiply-add per tap
     achieved = flops / (ms * 1e-3) / 1e12
@@ -217,6 +238,8 @@ def kernel_tile(prec):
     env = os.environ.get("BF_TILE")
     if env:
         return env
+    if prec == "fft":
+        return "fft"
     return "2x8i" if prec in ("bf16x3", "f16x2") else "2x4"
 
 
@@ -263,7 +286,7 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--tails-kappa", type=float, default=5.0,
                     help="search depth of the kappa-sigma tail leg (0 skips it)")
-    ap.add_argument("--extra-forms", default="f16x2",
+    ap.add_argument("--extra-forms", default="f16x2,fft",
                     help="comma-separated further precision forms to time and check ('' skips)")
     ap.add_argument("--cpu-offsets", type=int, default=1024, help="0 skips the oracle leg")
     ap.add_argument("--serve-segments", type=int, default=16,

@@ -65,10 +65,13 @@ typedef enum {
                     strip), undone by the MFMA scale operands; the rounded templates' sums
                     times the window mean are subtracted.  ~1% median, <=25% worst-case
                     relative error (short templates) */
-  BF_F16X2 = 3   /* fp16 hi+lo split of the templates, fp16 data with a power-of-two strip
+  BF_F16X2 = 3,  /* fp16 hi+lo split of the templates, fp16 data with a power-of-two strip
                     scale; h_hi*x + h_lo*x (two MFMA products per tap).  The data's fp16
                     rounding bounds the error: ~1e-4 to 7e-4 relative, stated bound
                     1e-3 */
+  BF_FFT = 4     /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
+                    real FFTs of length N = the smallest power of two >= max(2L, 1024);
+                    L <= 4096; same outputs as the direct forms (no tails) */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;

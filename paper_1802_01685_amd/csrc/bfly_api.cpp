@@ -67,8 +67,10 @@ bf_status check_desc(const bf_bank_desc* d) {
       d->shard_count > d->n_f0)
     return fail(BF_EINVAL, "need 0 <= shard_index < shard_count <= n_f0");
   if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8 &&
-      d->precision != BF_F16X2)
+      d->precision != BF_F16X2 && d->precision != BF_FFT)
     return fail(BF_EINVAL, "precision %d is not available", d->precision);
+  if (d->precision == BF_FFT && d->L > MAX_FFT_L)
+    return fail(BF_EINVAL, "the FFT form needs L <= %d", MAX_FFT_L);
   const double v[4] = {d->f0_min, d->f0_max, d->fdot_min, d->fdot_max};
   for (double x : v)
     if (!std::isfinite(x)) return fail(BF_EINVAL, "grid bounds must be finite");
@@ -106,6 +108,13 @@ void fill_geometry(const bf_bank_desc* d, GridDev* g, BankDev* b) {
   b->L_pad = (int32_t)round_up(d->L, 2 * chunk_taps(d->precision));
   b->n_chunks = b->L_pad / chunk_taps(d->precision);
   b->precision = d->precision;
+  b->fft_m = 0;
+  if (d->precision == BF_FFT) {
+    // real FFT length N = the smallest power of two >= 2L (at least 1024), M = N / 2
+    int32_t m = 512;
+    while (2 * m < 2 * d->L) m *= 2;
+    b->fft_m = m;
+  }
 }
 
 // The grid value numpy.linspace produces: i*step + start, the last point exactly stop.
@@ -241,6 +250,8 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
   }
   const bool with_tails = tails != nullptr;
+  if (with_tails && b.precision == P_FFT)
+    return fail(BF_EINVAL, "the tail search needs a direct-contraction bank, not the FFT form");
   if (with_tails && !(kappa >= 0.0f && std::isfinite(kappa)))
     return fail(BF_EINVAL, "kappa must be finite and >= 0");
   size_t need = table_bytes(n_segs);
@@ -303,7 +314,7 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   release_staging(stg, e == hipSuccess);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
 
-  HIP_TRY(prepare_main(b, sp), "hipFuncSetAttribute(k_main)");
+  if (b.precision != P_FFT) HIP_TRY(prepare_main(b, sp), "hipFuncSetAttribute(k_main)");
   TimingSet* te = nullptr;
   if (g_timing && (te = timing_slot(dev, &st)) == nullptr) return st;
   const int32_t xb =
@@ -332,6 +343,7 @@ size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails) {
     off = align256(off + sizeof(unsigned long long));
     off = align256(off + (size_t)b.K_pad * sizeof(float));
   }
+  if (b.precision == P_FFT) off = align256(off + fft_blocks(b, W) * (size_t)(b.fft_m + 2) * 8);
   return off;
 }
 
@@ -354,7 +366,10 @@ void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s, boo
     s->n_ok = (unsigned long long*)(base + off);
     off = align256(off + sizeof(unsigned long long));
     s->thr = (float*)(base + off);
+    off = align256(off + (size_t)b.K_pad * sizeof(float));
   }
+  s->xspec = nullptr;
+  if (b.precision == P_FFT) s->xspec = (float2*)(base + off);
 }
 
 bf_status check_params(const bf_search_params* p) {
@@ -381,6 +396,10 @@ SearchDev make_search(const BankDev& b, const bf_search_params* prm, int mode, f
   sp.hist_hi = prm->hist_hi;
   choose_tile(b.precision, mode, &sp.tm, &sp.tn, &sp.pipe);
   sp.n_wg = 32 * sp.tn * WG_WAVES;
+  if (b.precision == P_FFT) {
+    sp.tm = sp.tn = sp.pipe = 0;
+    sp.n_wg = 2 * b.fft_m - b.L + 1;   // valid outputs per overlap-save block
+  }
   return sp;
 }
 
@@ -402,6 +421,26 @@ bf_status device_slots(int* slots) {
 // waves: estimated makespan = ceil(items / slots) * (tiles of the largest range), plus a
 // small per-item cost (strip fill and flushes).  With at least 8 bins the count is a
 // multiple of 8, so that each XCD sweeps its own ranges (see the item order in k_main).
+// FFT form: items = blocks x ranges of whole f0 bins; two work-groups fit a CU.  Minimises
+// waves x (bins per range), preferring fewer ranges (each item transforms its block once).
+int32_t plan_fft_ranges(const BankDev& b, int64_t total_tiles, int slots) {
+  double best_cost = 1e300;
+  int32_t best_r = 1;
+  const int64_t conc = 2 * (int64_t)slots;
+  for (int32_t r = 1; r <= b.n_bins; ++r) {
+    const int64_t items = total_tiles * r;
+    if (items > (int64_t)0x7FFFFFFF) break;
+    const int64_t waves = (items + conc - 1) / conc;
+    const double cost = (double)waves * (double)((b.n_bins + r - 1) / r) + 0.01 * (double)waves;
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best_r = r;
+    }
+    if (items > 16 * conc) break;
+  }
+  return best_r;
+}
+
 constexpr int XCDS = 8;
 int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots, int tm) {
   double best_cost = 1e300;
@@ -451,6 +490,7 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
     d.hist = s[i].out.hist;
     d.n_degenerate = s[i].out.n_degenerate;
     d.spec_rows = (d.W + sp.t_block - 1) / sp.t_block;
+    d.xspec = s[i].xspec;
     const bf_tails* t = s[i].tails;
     d.sig_acc = t ? s[i].sig_acc : nullptr;
     d.n_ok = t ? s[i].n_ok : nullptr;
@@ -468,7 +508,8 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
   std::memset(hdr, 0, sizeof(BatchHdr));
   hdr->n_segs = n;
   hdr->total_tiles = tiles;
-  hdr->n_ranges = plan_ranges(b, tiles, slots, sp.tm);
+  hdr->n_ranges = b.precision == P_FFT ? plan_fft_ranges(b, tiles, slots)
+                                       : plan_ranges(b, tiles, slots, sp.tm);
   hdr->n_items = tiles * hdr->n_ranges;
   ti.n_items = hdr->n_items;
   return ti;
@@ -511,7 +552,10 @@ bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr*
   if (te) HIP_TRY(hipEventRecord(te->ev[2], stream), "hipEventRecord");
   HIP_TRY(launch_norms(table_dev, seg_slots, xb, b.L, sp.norm, stream), "k_norms launch");
   if (te) HIP_TRY(hipEventRecord(te->ev[3], stream), "hipEventRecord");
-  HIP_TRY(launch_main(table_dev, main_blocks, b, sp, stream), "k_main launch");
+  if (b.precision == P_FFT)
+    HIP_TRY(launch_fft_search(table_dev, main_blocks, b, sp, stream), "k_fft launch");
+  else
+    HIP_TRY(launch_main(table_dev, main_blocks, b, sp, stream), "k_main launch");
   if (te) HIP_TRY(hipEventRecord(te->ev[4], stream), "hipEventRecord");
   HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp, stream), "k_finalize launch");
   if (te) HIP_TRY(hipEventRecord(te->ev[5], stream), "hipEventRecord");
@@ -569,7 +613,10 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     if (((uintptr_t)dev_mem & 255) != 0) return fail(BF_EINVAL, "dev_mem not 256-byte aligned");
     if ((st = check_device_ptr(dev_mem, "dev_mem")) != BF_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_bank_gen(g, b, dev_mem, s), "k_bank_gen launch");
+    if (b.precision == P_FFT)
+      HIP_TRY(launch_fft_bank(g, b, dev_mem, s), "k_fft_bank launch");
+    else
+      HIP_TRY(launch_bank_gen(g, b, dev_mem, s), "k_bank_gen launch");
     unsigned int bad = 0;
     HIP_TRY(hipMemcpyAsync(&bad, (char*)dev_mem + bank_data_bytes(b) + bank_exp_bytes(b), sizeof bad,
                            hipMemcpyDeviceToHost, s),
@@ -810,7 +857,8 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
     if (n[i] < bank->dev.L) return fail(BF_EINVAL, "series shorter than L");
     int32_t tm = 0, tn = 0, pp = 0;
     choose_tile(bank->dev.precision, MODE_SEARCH, &tm, &tn, &pp);
-    const int64_t n_wg = 32 * (int64_t)tn * WG_WAVES;
+    const int64_t n_wg = bank->dev.precision == P_FFT ? 2 * (int64_t)bank->dev.fft_m - bank->dev.L + 1
+                                                       : 32 * (int64_t)tn * WG_WAVES;
     tiles += (n[i] - bank->dev.L + 1 + n_wg - 1) / n_wg;
   }
   int slots = 0;
@@ -818,7 +866,8 @@ bf_status bf_plan(const bf_bank* bank, const int64_t* n, int32_t n_segs, int32_t
   if (st != BF_OK) return st;
   int32_t tm = 0, tn = 0, pp = 0;
   choose_tile(bank->dev.precision, MODE_SEARCH, &tm, &tn, &pp);
-  const int32_t r = plan_ranges(bank->dev, tiles, slots, tm);
+  const int32_t r = bank->dev.precision == P_FFT ? plan_fft_ranges(bank->dev, tiles, slots)
+                                                 : plan_ranges(bank->dev, tiles, slots, tm);
   if (n_ranges) *n_ranges = r;
   if (n_items) *n_items = tiles * r;
   return BF_OK;

@@ -1,0 +1,441 @@
+// FFT-correlation form of the search (Sec. 2.2 and the Fig. 5 caption: the paper computes
+// the matched-filter correlations with FFTs on the GPU).
+//
+// Overlap-save with real FFTs of length N = 2M (a power of two >= 2L): block b of a series
+// covers x[tau_b, tau_b + N) with tau_b = b (N - L + 1); the circular cross-correlation of a
+// zero-padded template with the block equals the direct correlation d(tau_b + t, k) for
+// t = 0 .. N - L.  Template spectra H_k (N/2 + 1 bins, float32) are made once at bank
+// creation; each search transforms its data blocks once (X_b) and, per (block, template),
+// forms C = conj(H_k) X_b, runs one inverse real FFT and reduces the N - L + 1 valid outputs
+// straight from registers into the same butterfly output, spectrogram and spectrum as the
+// direct contraction (same packed keys, same fixed-point sums, same finalisation).
+//
+// A real FFT of length N runs as a complex FFT of length M on z[n] = x[2n] + i x[2n+1]
+// (even/odd split and the usual post-processing twiddles).  The complex FFT is a Stockham
+// autosort FFT in LDS with radix-16 passes and one smaller last pass (M = 512 .. 4096), one
+// work-group of 256 threads per transform; each thread holds one radix-R butterfly in
+// registers.  After the last inverse pass the thread keeps its 2R outputs in registers, at
+// fixed positions for every template, so the running maxima never leave registers.
+#include "bfly_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace bfly {
+
+namespace {
+
+constexpr int FT = 256;  // threads per work-group
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// exp(+-2 pi i f) for a fraction f in [0, 1) given exactly (a dyadic rational).
+template <bool INV>
+__device__ __forceinline__ float2 cis_rev(float f) {
+  float s, c;
+  sincospif(2.0f * f, &s, &c);
+  return make_float2(c, INV ? s : -s);
+}
+
+// cos and sin of 2 pi q / 16, q = 0..7.
+__device__ constexpr float C16[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
+                                     0.38268343236508978f, 0.0f, -0.38268343236508978f,
+                                     -0.70710678118654752f, -0.92387953251128674f};
+__device__ constexpr float S16[8] = {0.0f, 0.38268343236508978f, 0.70710678118654752f,
+                                     0.92387953251128674f, 1.0f, 0.92387953251128674f,
+                                     0.70710678118654752f, 0.38268343236508978f};
+
+constexpr int bitrev(int i, int R) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of size R (2, 4, 8 or 16), natural order in and out: radix-2
+// decimation in time after a bit-reversal permutation.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  float2 t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[bitrev(i, R)] = v[i];
+#pragma unroll
+  for (int s = 2; s <= R; s <<= 1) {
+    const int h = s / 2;
+#pragma unroll
+    for (int g = 0; g < R; g += s)
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const int q = k * (16 / s);
+        const float2 w = make_float2(C16[q], INV ? S16[q] : -S16[q]);
+        const float2 a = t[g + k];
+        const float2 b = q == 0 ? t[g + k + h] : cmul(t[g + k + h], w);
+        t[g + k] = cadd(a, b);
+        t[g + k + h] = csub(a, b);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = t[i];
+}
+
+// One Stockham pass of radix R over M points in LDS, sub-transform size Ns before the pass:
+// butterfly j (< M/R) reads buf[j + r M/R], twiddles input r by w^r with
+// w = exp(-+2 pi i (j mod Ns) / (Ns R)), transforms, and writes to buf[(j - j mod Ns) R +
+// j mod Ns + r Ns].  With KEEP the outputs stay in v (the last pass) and are not written.
+template <int M, int R, bool INV, bool KEEP>
+__device__ __forceinline__ void fft_pass(float2* buf, int Ns, float2 (&v)[R]) {
+  constexpr int NB = M / R;
+  static_assert(NB <= FT && FT % NB == 0, "one butterfly per thread at most");
+  const int j = threadIdx.x;
+  const bool act = j < NB;
+  const int jm = j & (Ns - 1);
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = buf[j + r * NB];
+    if (Ns > 1) {
+      // w^r from w, w^2, w^4, w^8 (at most three products per power)
+      const float2 w1 = cis_rev<INV>((float)jm / (float)(Ns * R));
+      const float2 w2 = cmul(w1, w1);
+      const float2 w4 = cmul(w2, w2);
+      const float2 w8 = cmul(w4, w4);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = make_float2(1.0f, 0.0f);
+        bool first = true;
+        if (r & 1) { w = w1; first = false; }
+        if (r & 2) { w = first ? w2 : cmul(w, w2); first = false; }
+        if (r & 4) { w = first ? w4 : cmul(w, w4); first = false; }
+        if (r & 8) { w = first ? w8 : cmul(w, w8); first = false; }
+        v[r] = cmul(v[r], w);
+      }
+    }
+    dft<R, INV>(v);
+  }
+  __syncthreads();
+  if (!KEEP) {
+    if (act) {
+      const int base = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[r];
+    }
+    __syncthreads();
+  }
+}
+
+// The pass schedule: radix-16 passes, then the remaining factor (M = 512: 16 16 2,
+// 1024: 16 16 4, 2048: 16 16 8, 4096: 16 16 16).  Every last pass has M / R = 256.
+template <int M> struct LastRadix { static constexpr int R = M / 256; };
+
+// Complex FFT of M points in buf (natural order in).  All passes write buf when out is
+// not kept; otherwise the last pass leaves thread j with outputs j + 256 r in out[r].
+template <int M, bool INV, bool KEEP>
+__device__ __forceinline__ void fft_run(float2* buf, float2 (&out)[LastRadix<M>::R]) {
+  float2 v16[16];
+  fft_pass<M, 16, INV, false>(buf, 1, v16);
+  fft_pass<M, 16, INV, false>(buf, 16, v16);
+  fft_pass<M, LastRadix<M>::R, INV, KEEP>(buf, 256, out);
+}
+
+// Forward real FFT of N = 2M real samples staged as z[n] = (x[2n], x[2n+1]) in buf:
+// writes X[k], k = 0..M, to dst (global).
+template <int M>
+__device__ __forceinline__ void rfft_post(float2* buf, float2* __restrict__ dst) {
+  float2 out[LastRadix<M>::R];
+  fft_run<M, false, false>(buf, out);
+  for (int k = threadIdx.x; k <= M; k += FT) {
+    const float2 zk = buf[k & (M - 1)];
+    const float2 zc = cconj(buf[(M - k) & (M - 1)]);
+    const float2 e = cscale(cadd(zk, zc), 0.5f);
+    const float2 d = cscale(csub(zk, zc), 0.5f);
+    const float2 o = make_float2(d.y, -d.x);                     // d / i
+    const float2 w = cis_rev<false>((float)k / (float)(2 * M));   // exp(-2 pi i k / N)
+    dst[k] = cadd(e, cmul(w, o));
+  }
+}
+
+// One template sample in float64, with the same formula as the direct bank:
+// cos(2 pi frac(f0 t + fdot t^2 / 2)), t = n / fs.
+__device__ __forceinline__ double template_sample(double fs, double f0, double fdot, int n) {
+  const double t = (double)n / fs;
+  double phi = f0 * t + 0.5 * fdot * (t * t);
+  phi = phi - floor(phi);
+  return cos(2.0 * 3.141592653589793 * phi);
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// Bank spectra: one work-group per template builds the zero-mean unit-norm template in
+// float64, rounds it to float32 and stores its real-FFT spectrum (row stride M + 2).
+template <int M>
+__global__ __launch_bounds__(FT) void k_fft_bank(GridDev g, BankDev b, float2* spectra,
+                                                 unsigned int* bad) {
+  __shared__ float2 buf[M];
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
+  const bool real = k < b.K;
+  double f0 = 0.0, fdot = 0.0, mu = 0.0, nrm = 1.0;
+  if (real) {
+    const int64_t il = k / g.n_fdot;
+    const int j = (int)(k % g.n_fdot);
+    const int64_t ig = g.f0_lo + il;
+    f0 = (g.n_f0 > 1 && ig == g.n_f0 - 1) ? g.f0_max : (double)ig * g.f0_step + g.f0_min;
+    fdot = (g.n_fdot > 1 && j == g.n_fdot - 1) ? g.fdot_max
+                                               : (double)j * g.fdot_step + g.fdot_min;
+    double s1 = 0.0;
+    for (int n = threadIdx.x; n < b.L; n += FT) s1 += template_sample(g.fs, f0, fdot, n);
+    mu = block_sum_d(s1, red) / (double)b.L;
+    double s2 = 0.0;
+    for (int n = threadIdx.x; n < b.L; n += FT) {
+      const double v = template_sample(g.fs, f0, fdot, n) - mu;
+      s2 += v * v;
+    }
+    s2 = block_sum_d(s2, red);
+    nrm = sqrt(s2);
+    if (!(s2 > 1e-18 * (double)b.L)) {
+      if (threadIdx.x == 0) atomicAdd(bad, 1u);
+      nrm = 1.0;
+    }
+  }
+  for (int n = threadIdx.x; n < M; n += FT) {
+    float2 z = make_float2(0.0f, 0.0f);
+    if (real && 2 * n < b.L) z.x = (float)((template_sample(g.fs, f0, fdot, 2 * n) - mu) / nrm);
+    if (real && 2 * n + 1 < b.L)
+      z.y = (float)((template_sample(g.fs, f0, fdot, 2 * n + 1) - mu) / nrm);
+    buf[n] = z;
+  }
+  __syncthreads();
+  rfft_post<M>(buf, spectra + k * (int64_t)(M + 2));
+}
+
+// Data spectra: one work-group per (series, block) tile, persistent over the batch's tiles.
+template <int M>
+__global__ __launch_bounds__(FT) void k_fft_data(const BatchHdr* __restrict__ hdr, BankDev b) {
+  __shared__ float2 buf[M];
+  const SegDesc* segs = hdr_segs(hdr);
+  const int64_t n_tiles = hdr->total_tiles;
+  const int valid = 2 * M - b.L + 1;
+  for (int64_t tt = blockIdx.x; tt < n_tiles; tt += gridDim.x) {
+    int lo = 0, hi = hdr->n_segs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
+    }
+    const SegDesc& sg = segs[lo];
+    const int64_t tau0 = (tt - sg.tile0) * valid;
+    for (int n = threadIdx.x; n < M; n += FT) {
+      const int64_t i0 = tau0 + 2 * n, i1 = i0 + 1;
+      float a = i0 < sg.n ? sg.x[i0] : 0.0f;
+      float c = i1 < sg.n ? sg.x[i1] : 0.0f;
+      buf[n] = make_float2(isfinite(a) ? a : 0.0f, isfinite(c) ? c : 0.0f);
+    }
+    __syncthreads();
+    rfft_post<M>(buf, sg.xspec + (tt - sg.tile0) * (int64_t)(M + 2));
+    __syncthreads();
+  }
+}
+
+// Position within the block of a thread's real output o: y[tid + 256 r] holds outputs
+// 2 (tid + 256 r) (real part) and 2 (tid + 256 r) + 1 (imaginary part), o = 2 r + part.
+__device__ __forceinline__ int out_pos(int o) { return 2 * ((int)threadIdx.x + FT * (o >> 1)) + (o & 1); }
+
+// Spectrogram / spectrum flush of one f0 bin for this thread's outputs.
+template <int NO>
+__device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p, int bin,
+                                          const float (&binmax)[NO], int64_t tau_base,
+                                          int valid, float scale) {
+  unsigned long long fix = 0ull;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int64_t tau = tau_base + out_pos(o);
+    if (out_pos(o) < valid && tau < sg.W) {
+      const double inv = sg.inv_norm[tau];
+      if (inv > 0.0) {
+        const float s = (float)((double)binmax[o] * (double)scale * inv);
+        if (sg.spec) {
+          const int64_t at = (int64_t)bin * sg.spec_rows + tau / p.t_block;
+          if (p.t_block == 1)
+            sg.spec[at] = s;
+          else
+            atomicMax((unsigned int*)sg.spec + at, __float_as_uint(s));
+        }
+        fix += (unsigned long long)__double2ll_rn((double)s * SPEC_FIX_SCALE);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(fix & 0xFFFFFFFFull), o, 64);
+    const unsigned hi = __shfl_xor((unsigned)(fix >> 32), o, 64);
+    fix += ((unsigned long long)hi << 32) | lo;
+  }
+  if ((threadIdx.x & 63) == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
+}
+
+// The search: work item = (series, block, range of whole f0 bins), numbered range-fastest;
+// persistent over the batch's items.  Per template of the range: C = conj(H_k) X_b, the
+// inverse real FFT, and the running reductions of the valid outputs.
+template <int M>
+__global__ __launch_bounds__(FT) void k_fft_main(const BatchHdr* __restrict__ hdr, BankDev b,
+                                                 SearchDev p) {
+  constexpr int R = LastRadix<M>::R;
+  constexpr int NO = 2 * R;             // real outputs per thread
+  constexpr int NP = (M / 2 + FT) / FT; // spectrum pairs per thread (M / 2 + 1 pairs)
+  __shared__ float2 xs[M + 2];
+  __shared__ float2 buf[M];
+  const SegDesc* segs = hdr_segs(hdr);
+  const float2* spectra = (const float2*)b.data;
+  const int n_ranges = hdr->n_ranges;
+  const int64_t n_items = hdr->n_items;
+  const int valid = 2 * M - b.L + 1;
+  const int tid = threadIdx.x;
+  const float scale = 1.0f / (float)M;
+  const int nfd = b.n_fdot;
+
+  // post-processing twiddles exp(+2 pi i p / N) of this thread's spectrum pairs
+  float2 wp[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int pp = tid + q * FT;
+    wp[q] = cis_rev<true>((float)(pp <= M / 2 ? pp : 0) / (float)(2 * M));
+  }
+
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int rg = (int)(item % n_ranges);
+    const int64_t tt = item / n_ranges;
+    int lo = 0, hi = hdr->n_segs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
+    }
+    const SegDesc& sg = segs[lo];
+    const int64_t blk = tt - sg.tile0;
+    const int64_t tau_base = blk * valid;
+    const int b_lo = (int)((int64_t)rg * b.n_bins / n_ranges);
+    const int b_hi = (int)((int64_t)(rg + 1) * b.n_bins / n_ranges);
+    const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
+    for (int k = tid; k <= M; k += FT) xs[k] = xsrc[k];
+    __syncthreads();
+
+    float best[NO], binmax[NO];
+    int bestk[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      best[o] = -1.0f;
+      bestk[o] = -1;
+      binmax[o] = 0.0f;
+    }
+    const int64_t k_lo = (int64_t)b_lo * nfd, k_hi = (int64_t)b_hi * nfd;
+    for (int64_t k = k_lo; k < k_hi; ++k) {
+      const float2* hk = spectra + k * (int64_t)(M + 2);
+      // Y[p] and Y[M - p] from C = conj(H) X at bins p and M - p
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int pp = tid + q * FT;
+        if (pp <= M / 2) {
+          const int p2 = M - pp;
+          const float2 c1 = cmul(cconj(hk[pp]), xs[pp]);
+          const float2 c2 = cmul(cconj(hk[p2]), xs[p2]);
+          const float2 e = cscale(cadd(c1, cconj(c2)), 0.5f);
+          const float2 d = cscale(csub(c1, cconj(c2)), 0.5f);
+          const float2 o = cmul(d, wp[q]);
+          buf[pp] = make_float2(e.x - o.y, e.y + o.x);                 // E + iO
+          if (pp != 0 && pp != M / 2) buf[p2] = make_float2(e.x + o.y, o.x - e.y);  // E* + iO*
+        }
+      }
+      __syncthreads();
+      float2 y[R];
+      fft_run<M, true, true>(buf, y);
+      // running maxima over the templates, lowest k on ties (k increases, strict >)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float a0 = fabsf(y[r].x), a1 = fabsf(y[r].y);
+        const bool g0 = a0 > best[2 * r], g1 = a1 > best[2 * r + 1];
+        best[2 * r] = g0 ? a0 : best[2 * r];
+        bestk[2 * r] = g0 ? (int)k : bestk[2 * r];
+        best[2 * r + 1] = g1 ? a1 : best[2 * r + 1];
+        bestk[2 * r + 1] = g1 ? (int)k : bestk[2 * r + 1];
+        binmax[2 * r] = fmaxf(binmax[2 * r], a0);
+        binmax[2 * r + 1] = fmaxf(binmax[2 * r + 1], a1);
+      }
+      if ((k + 1) % nfd == 0) {
+        fft_flush<NO>(sg, p, (int)(k / nfd), binmax, tau_base, valid, scale);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) binmax[o] = 0.0f;
+      }
+    }
+    // per-offset maxima: one packed atomic per valid output (value first, then lower k)
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const int64_t tau = tau_base + out_pos(o);
+      if (out_pos(o) < valid && tau < sg.W && bestk[o] >= 0) {
+        const unsigned int kg = (unsigned int)(b.k_offset + bestk[o]);
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(best[o] * scale) << 32) |
+            (0xFFFFFFFFull - kg);
+        atomicMax(sg.mkey + tau, key);
+      }
+    }
+    __syncthreads();   // xs is refilled by the next item
+  }
+}
+
+template <int M>
+hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsigned* bad,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_fft_bank<M>, dim3((unsigned)b.K_pad), dim3(FT), 0, s, g, b,
+                     (float2*)dst, bad);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                               const SearchDev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(FT), 0, s, hdr, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fft_main<M>, dim3((unsigned)blocks), dim3(FT), 0, s, hdr, b, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define BFLY_FFT_DISPATCH(FN, ...)                      \
+  do {                                                  \
+    switch (b.fft_m) {                                  \
+      case 512: return FN<512>(__VA_ARGS__);            \
+      case 1024: return FN<1024>(__VA_ARGS__);          \
+      case 2048: return FN<2048>(__VA_ARGS__);          \
+      case 4096: return FN<4096>(__VA_ARGS__);          \
+      default: return hipErrorInvalidValue;             \
+    }                                                   \
+  } while (0)
+
+hipError_t launch_fft_bank(const GridDev& g, const BankDev& b, void* dst, hipStream_t s) {
+  unsigned int* bad = (unsigned int*)((char*)dst + bank_data_bytes(b));
+  hipError_t e = hipMemsetAsync(bad, 0, 256, s);
+  if (e != hipSuccess) return e;
+  BFLY_FFT_DISPATCH(launch_fft_bank_t, g, b, dst, bad, s);
+}
+
+hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                             const SearchDev& p, hipStream_t s) {
+  if (blocks < 1) return hipSuccess;
+  BFLY_FFT_DISPATCH(launch_fft_search_t, hdr, blocks, b, p, s);
+}
+
+}  // namespace bfly

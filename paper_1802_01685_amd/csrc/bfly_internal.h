@@ -20,11 +20,12 @@ constexpr int KCH = 16;                       // taps per chunk, FP32 and BF16 f
 constexpr int KCH_FP8 = 64;                   // taps per chunk, FP8 form
 constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG + L_pad
 constexpr int MAX_L = 8192;
+constexpr int MAX_FFT_L = 4096;              // FFT form: N = 2M <= 8192
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
 constexpr double SIGMA_FIX_SCALE = 68719476736.0;   // 2^36: fixed-point sums of rho^2
 
-enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3 };
+enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4 };
 
 // F16X2: templates are stored as fp16 hi + lo of h * 2^F16_TEMPLATE_EXP.
 constexpr int F16_TEMPLATE_EXP = 10;
@@ -51,6 +52,7 @@ struct SegDesc {
   uint32_t* hist;
   int64_t* n_degenerate;
   int64_t spec_rows;    // ceil(W / t_block)
+  float2* xspec;        // FFT form: [n_tiles][M + 2] spectra of the data blocks
   // kappa-sigma tails (null unless the search extracts them)
   unsigned long long* sig_acc;   // [K_pad] fixed-point sums of rho^2 per template
   unsigned long long* n_ok;      // [1] non-degenerate offsets
@@ -94,6 +96,7 @@ struct BankDev {
   int32_t n_fdot;       // templates per spectrogram bin
   int32_t n_bins;
   int32_t precision;
+  int32_t fft_m;        // FFT form: complex FFT length M = N / 2 (N = real FFT length)
 };
 
 // Grid description for bank generation (float64).
@@ -122,6 +125,7 @@ enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2 };
 // Bytes of the quantised templates, of the FP8 exponents, and of the whole bank allocation
 // (templates, exponents, then a 256-byte status word).
 inline size_t bank_data_bytes(const BankDev& b) {
+  if (b.precision == P_FFT) return (size_t)b.K_pad * (size_t)(b.fft_m + 2) * 8;  // spectra
   return (size_t)b.K_pad * (size_t)b.L_pad * (b.precision == P_FP8 ? 1 : 4);
 }
 // FP8 side tables after the codes: int32 exponent e_k [K_pad], then float sum of the
@@ -154,6 +158,12 @@ hipError_t launch_finalize(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blo
 hipError_t launch_sigma(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
                         const SearchDev& p, hipStream_t s);
 size_t main_lds_bytes(int precision, int L_pad, int n_wg);
+
+// FFT form (bfly_fft.hip): template spectra at bank creation; a search transforms its data
+// blocks and runs the fused correlation/reduction kernel (persistent over hdr's items).
+hipError_t launch_fft_bank(const GridDev& g, const BankDev& b, void* dst, hipStream_t s);
+hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                             const SearchDev& p, hipStream_t s);
 
 // Two-detector coincidence (bfly_coinc.hip).  A channel's tail list (device) and its output
 // counts per f0 bin; the workspace of the offset buckets of channel B.

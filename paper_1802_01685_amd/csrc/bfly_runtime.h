@@ -39,6 +39,7 @@ struct SeriesBufs {
   unsigned long long* n_ok = nullptr;
   float* thr = nullptr;
   const bf_tails* tails = nullptr;
+  float2* xspec = nullptr;     // FFT form: data block spectra (workspace)
 };
 
 // Bytes of one series' workspace part (prefix sums, counts, norms, maxima, spectrum sums;
@@ -57,6 +58,12 @@ SearchDev make_search(const BankDev& b, const bf_search_params* p, int mode = MO
                       float kappa = 0.0f);
 bf_status device_slots(int* slots);
 int32_t plan_ranges(const BankDev& b, int64_t total_tiles, int slots, int tm);
+int32_t plan_fft_ranges(const BankDev& b, int64_t total_tiles, int slots);
+// FFT form: overlap-save blocks of a series with W offsets.
+inline int64_t fft_blocks(const BankDev& b, int64_t W) {
+  const int64_t v = 2 * (int64_t)b.fft_m - b.L + 1;
+  return (W + v - 1) / v;
+}
 
 // Fills a host batch table (hdr followed by the SegDescs) for the series s[0..n-1].
 struct TableInfo {

@@ -379,7 +379,7 @@ bf_status bf_server_create(const bf_bank* bank, const bf_server_desc* desc, bf_s
                        desc->hbm_budget_bytes);
     }
     s->arena.reset(desc->hbm_budget_bytes & ~(size_t)255);
-    if ((e = prepare_main(bank->dev, s->sp)) != hipSuccess) {
+    if (bank->dev.precision != P_FFT && (e = prepare_main(bank->dev, s->sp)) != hipSuccess) {
       free_server(s);
       return hip_error(e, "hipFuncSetAttribute(k_main)");
     }

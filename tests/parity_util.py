@@ -14,7 +14,8 @@ from oracle import bfly_oracle as O
 # codes each carry up to 2^-4 relative rounding, so a correlation carries a random error of
 # about 0.05 / sqrt(L) in rho: about 1% of m at the median, and up to ~7% of m (~15% of a
 # small spectrogram entry, relative to the 1/sqrt(L) floor) on templates of 37-64 taps.
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fp8": 0.2}
+# The FFT form computes in float32 (spectra, transforms, products): the FP32 bound.
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fp8": 0.2, "fft": 1e-5}
 
 
 def to_np(out: dict) -> dict:

@@ -52,6 +52,13 @@ def test_bank_bytes_and_validation_on_host(lib):
     # one byte per tap, then an int32 exponent and a float template sum per template, then
     # the status word
     assert lib.bank_bytes(d8) == 65536 * 4096 + 65536 * 8 + 256
+    # FFT form: a float32 complex spectrum of N/2 + 1 bins per template (rows of N/2 + 2),
+    # N = 8192 for L = 4096
+    df = lib.make_desc(bank_params(2), "fft")
+    assert lib.bank_bytes(df) == 65536 * (4096 + 2) * 8 + 256
+    df.L = 4097
+    with pytest.raises(lib.BflyError):
+        lib.bank_bytes(df)
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
         q = lib.make_desc(bank_params(2), "fp32")
