@@ -281,7 +281,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32", "fft"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--tails-kappa", type=float, default=5.0,

@@ -12,9 +12,9 @@
 //
 // A real FFT of length N runs as a complex FFT of length M on z[n] = x[2n] + i x[2n+1]
 // (even/odd split and the usual post-processing twiddles).  The complex FFT is a Stockham
-// autosort FFT in LDS with radix-16 passes and one smaller last pass (M = 512 .. 4096), one
-// work-group of 256 threads per transform; each thread holds one radix-R butterfly in
-// registers.  After the last inverse pass the thread keeps its 2R outputs in registers, at
+// autosort FFT in LDS (M = 512 .. 4096): one work-group of M/8 threads per transform, radix-8
+// passes after a first pass of radix 2, 4 or 8; each thread holds its butterflies in
+// registers.  After the last inverse pass the thread keeps its 16 outputs in registers, at
 // fixed positions for every template, so the running maxima never leave registers.
 #include "bfly_internal.h"
 
@@ -23,8 +23,6 @@
 namespace bfly {
 
 namespace {
-
-constexpr int FT = 256;  // threads per work-group
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -85,73 +83,113 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
+// FFT plan for M points: T = M / 8 threads per work-group, P passes; the first pass has
+// radix R0 = M / 8^(P-1) (Ns = 1, T or more butterflies per thread, no twiddles), every
+// further pass is radix 8 with one butterfly per thread; the last pass leaves thread j with
+// points j + T r, r < 8.  (512: 8 8 8; 1024: 2 8 8 8; 2048: 4 8 8 8; 4096: 8 8 8 8.)
+template <int M> struct Plan {
+  static constexpr int T = M / 8;
+  static constexpr int P = M <= 512 ? 3 : 4;
+  static constexpr int R0 = P == 3 ? M / 64 : M / 512;
+};
+
+// LDS index of FFT point i: one pad slot after every 8 points, so that the strided writes
+// of the passes fall on distinct banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
+template <int M> struct Padded { static constexpr int n = M + M / 8; };
+
+// The twiddle base of a pass for butterfly j: exp(-+2 pi i (j mod Ns) / (Ns R)).
+template <bool INV>
+__device__ __forceinline__ float2 pass_twiddle(int j, int Ns, int R) {
+  return cis_rev<INV>((float)(j & (Ns - 1)) / (float)(Ns * R));
+}
+
 // One Stockham pass of radix R over M points in LDS, sub-transform size Ns before the pass:
-// butterfly j (< M/R) reads buf[j + r M/R], twiddles input r by w^r with
-// w = exp(-+2 pi i (j mod Ns) / (Ns R)), transforms, and writes to buf[(j - j mod Ns) R +
-// j mod Ns + r Ns].  With KEEP the outputs stay in v (the last pass) and are not written.
+// butterfly j (< M/R) reads point j + r M/R, twiddles input r by w1^r (w1 = pass_twiddle of
+// j), transforms, and writes point (j - j mod Ns) R + j mod Ns + r Ns.  Thread t runs
+// butterflies t, t + T, ...  With KEEP the outputs stay in v and are not written back.
 template <int M, int R, bool INV, bool KEEP>
-__device__ __forceinline__ void fft_pass(float2* buf, int Ns, float2 (&v)[R]) {
+__device__ __forceinline__ void fft_pass(float2* buf, int Ns, float2 w1,
+                                         float2 (&v)[M / R / Plan<M>::T][R]) {
+  constexpr int T = Plan<M>::T;
   constexpr int NB = M / R;
-  static_assert(NB <= FT && FT % NB == 0, "one butterfly per thread at most");
-  const int j = threadIdx.x;
-  const bool act = j < NB;
-  const int jm = j & (Ns - 1);
-  if (act) {
+  constexpr int BPT = NB / T;
+  static_assert(BPT >= 1 && NB % T == 0, "whole butterflies per thread");
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = buf[j + r * NB];
+  for (int t = 0; t < BPT; ++t) {
+    const int j = threadIdx.x + t * T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[t][r] = buf[pad(j + r * NB)];
     if (Ns > 1) {
-      // w^r from w, w^2, w^4, w^8 (at most three products per power)
-      const float2 w1 = cis_rev<INV>((float)jm / (float)(Ns * R));
-      const float2 w2 = cmul(w1, w1);
-      const float2 w4 = cmul(w2, w2);
-      const float2 w8 = cmul(w4, w4);
+      // w1^r as a running product (few live registers; at most R - 2 roundings)
+      float2 w = w1;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = make_float2(1.0f, 0.0f);
-        bool first = true;
-        if (r & 1) { w = w1; first = false; }
-        if (r & 2) { w = first ? w2 : cmul(w, w2); first = false; }
-        if (r & 4) { w = first ? w4 : cmul(w, w4); first = false; }
-        if (r & 8) { w = first ? w8 : cmul(w, w8); first = false; }
-        v[r] = cmul(v[r], w);
+        v[t][r] = cmul(v[t][r], w);
+        if (r + 1 < R) w = cmul(w, w1);
       }
     }
-    dft<R, INV>(v);
+    dft<R, INV>(v[t]);
   }
   __syncthreads();
   if (!KEEP) {
-    if (act) {
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+      const int j = threadIdx.x + t * T;
+      const int jm = j & (Ns - 1);
       const int base = (j - jm) * R + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[r];
+      for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = v[t][r];
     }
     __syncthreads();
   }
 }
 
-// The pass schedule: radix-16 passes, then the remaining factor (M = 512: 16 16 2,
-// 1024: 16 16 4, 2048: 16 16 8, 4096: 16 16 16).  Every last pass has M / R = 256.
-template <int M> struct LastRadix { static constexpr int R = M / 256; };
+// The thread's twiddle bases of passes 2..P.
+template <int M, bool INV>
+struct PassTw {
+  float2 w[3];
+  __device__ __forceinline__ void init() {
+    int Ns = Plan<M>::R0;
+#pragma unroll
+    for (int p = 0; p < Plan<M>::P - 1; ++p) {
+      w[p] = pass_twiddle<INV>(threadIdx.x, Ns, 8);
+      Ns *= 8;
+    }
+  }
+};
 
-// Complex FFT of M points in buf (natural order in).  All passes write buf when out is
-// not kept; otherwise the last pass leaves thread j with outputs j + 256 r in out[r].
+// Complex FFT of M points in buf (padded, natural order in).  All passes write buf when
+// not KEEP; with KEEP the last pass leaves thread j with points j + T r in out[r].
 template <int M, bool INV, bool KEEP>
-__device__ __forceinline__ void fft_run(float2* buf, float2 (&out)[LastRadix<M>::R]) {
-  float2 v16[16];
-  fft_pass<M, 16, INV, false>(buf, 1, v16);
-  fft_pass<M, 16, INV, false>(buf, 16, v16);
-  fft_pass<M, LastRadix<M>::R, INV, KEEP>(buf, 256, out);
+__device__ __forceinline__ void fft_run(float2* buf, const PassTw<M, INV>& tw,
+                                        float2 (&out)[8]) {
+  constexpr int R0 = Plan<M>::R0;
+  float2 v0[M / R0 / Plan<M>::T][R0];
+  fft_pass<M, R0, INV, false>(buf, 1, make_float2(1.0f, 0.0f), v0);
+  float2 v[1][8];
+  int Ns = R0;
+#pragma unroll
+  for (int p = 0; p < Plan<M>::P - 2; ++p) {
+    fft_pass<M, 8, INV, false>(buf, Ns, tw.w[p], v);
+    Ns *= 8;
+  }
+  fft_pass<M, 8, INV, KEEP>(buf, Ns, tw.w[Plan<M>::P - 2], v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) out[r] = v[0][r];
 }
 
 // Forward real FFT of N = 2M real samples staged as z[n] = (x[2n], x[2n+1]) in buf:
 // writes X[k], k = 0..M, to dst (global).
 template <int M>
 __device__ __forceinline__ void rfft_post(float2* buf, float2* __restrict__ dst) {
-  float2 out[LastRadix<M>::R];
-  fft_run<M, false, false>(buf, out);
-  for (int k = threadIdx.x; k <= M; k += FT) {
-    const float2 zk = buf[k & (M - 1)];
-    const float2 zc = cconj(buf[(M - k) & (M - 1)]);
+  float2 out[8];
+  PassTw<M, false> tw;
+  tw.init();
+  fft_run<M, false, false>(buf, tw, out);
+  for (int k = threadIdx.x; k <= M; k += Plan<M>::T) {
+    const float2 zk = buf[pad(k & (M - 1))];
+    const float2 zc = cconj(buf[pad((M - k) & (M - 1))]);
     const float2 e = cscale(cadd(zk, zc), 0.5f);
     const float2 d = cscale(csub(zk, zc), 0.5f);
     const float2 o = make_float2(d.y, -d.x);                     // d / i
@@ -169,23 +207,28 @@ __device__ __forceinline__ double template_sample(double fs, double f0, double f
   return cos(2.0 * 3.141592653589793 * phi);
 }
 
+// Sum over the work-group's threads (NW waves of 64).
+template <int NW>
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int wave = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += red[w];
+  return t;
 }
 
 // Bank spectra: one work-group per template builds the zero-mean unit-norm template in
 // float64, rounds it to float32 and stores its real-FFT spectrum (row stride M + 2).
 template <int M>
-__global__ __launch_bounds__(FT) void k_fft_bank(GridDev g, BankDev b, float2* spectra,
-                                                 unsigned int* bad) {
-  __shared__ float2 buf[M];
-  __shared__ double red[4];
+__global__ __launch_bounds__(Plan<M>::T) void k_fft_bank(GridDev g, BankDev b,
+                                                          float2* spectra, unsigned int* bad) {
+  constexpr int T = Plan<M>::T;
+  __shared__ float2 buf[Padded<M>::n];
+  __shared__ double red[T / 64];
   const int64_t k = blockIdx.x;
   const bool real = k < b.K;
   double f0 = 0.0, fdot = 0.0, mu = 0.0, nrm = 1.0;
@@ -197,26 +240,26 @@ __global__ __launch_bounds__(FT) void k_fft_bank(GridDev g, BankDev b, float2* s
     fdot = (g.n_fdot > 1 && j == g.n_fdot - 1) ? g.fdot_max
                                                : (double)j * g.fdot_step + g.fdot_min;
     double s1 = 0.0;
-    for (int n = threadIdx.x; n < b.L; n += FT) s1 += template_sample(g.fs, f0, fdot, n);
-    mu = block_sum_d(s1, red) / (double)b.L;
+    for (int n = threadIdx.x; n < b.L; n += T) s1 += template_sample(g.fs, f0, fdot, n);
+    mu = block_sum_d<T / 64>(s1, red) / (double)b.L;
     double s2 = 0.0;
-    for (int n = threadIdx.x; n < b.L; n += FT) {
+    for (int n = threadIdx.x; n < b.L; n += T) {
       const double v = template_sample(g.fs, f0, fdot, n) - mu;
       s2 += v * v;
     }
-    s2 = block_sum_d(s2, red);
+    s2 = block_sum_d<T / 64>(s2, red);
     nrm = sqrt(s2);
     if (!(s2 > 1e-18 * (double)b.L)) {
       if (threadIdx.x == 0) atomicAdd(bad, 1u);
       nrm = 1.0;
     }
   }
-  for (int n = threadIdx.x; n < M; n += FT) {
+  for (int n = threadIdx.x; n < M; n += T) {
     float2 z = make_float2(0.0f, 0.0f);
     if (real && 2 * n < b.L) z.x = (float)((template_sample(g.fs, f0, fdot, 2 * n) - mu) / nrm);
     if (real && 2 * n + 1 < b.L)
       z.y = (float)((template_sample(g.fs, f0, fdot, 2 * n + 1) - mu) / nrm);
-    buf[n] = z;
+    buf[pad(n)] = z;
   }
   __syncthreads();
   rfft_post<M>(buf, spectra + k * (int64_t)(M + 2));
@@ -224,8 +267,10 @@ __global__ __launch_bounds__(FT) void k_fft_bank(GridDev g, BankDev b, float2* s
 
 // Data spectra: one work-group per (series, block) tile, persistent over the batch's tiles.
 template <int M>
-__global__ __launch_bounds__(FT) void k_fft_data(const BatchHdr* __restrict__ hdr, BankDev b) {
-  __shared__ float2 buf[M];
+__global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restrict__ hdr,
+                                                          BankDev b) {
+  constexpr int T = Plan<M>::T;
+  __shared__ float2 buf[Padded<M>::n];
   const SegDesc* segs = hdr_segs(hdr);
   const int64_t n_tiles = hdr->total_tiles;
   const int valid = 2 * M - b.L + 1;
@@ -237,11 +282,11 @@ __global__ __launch_bounds__(FT) void k_fft_data(const BatchHdr* __restrict__ hd
     }
     const SegDesc& sg = segs[lo];
     const int64_t tau0 = (tt - sg.tile0) * valid;
-    for (int n = threadIdx.x; n < M; n += FT) {
+    for (int n = threadIdx.x; n < M; n += T) {
       const int64_t i0 = tau0 + 2 * n, i1 = i0 + 1;
       float a = i0 < sg.n ? sg.x[i0] : 0.0f;
       float c = i1 < sg.n ? sg.x[i1] : 0.0f;
-      buf[n] = make_float2(isfinite(a) ? a : 0.0f, isfinite(c) ? c : 0.0f);
+      buf[pad(n)] = make_float2(isfinite(a) ? a : 0.0f, isfinite(c) ? c : 0.0f);
     }
     __syncthreads();
     rfft_post<M>(buf, sg.xspec + (tt - sg.tile0) * (int64_t)(M + 2));
@@ -249,25 +294,31 @@ __global__ __launch_bounds__(FT) void k_fft_data(const BatchHdr* __restrict__ hd
   }
 }
 
-// Position within the block of a thread's real output o: y[tid + 256 r] holds outputs
-// 2 (tid + 256 r) (real part) and 2 (tid + 256 r) + 1 (imaginary part), o = 2 r + part.
-__device__ __forceinline__ int out_pos(int o) { return 2 * ((int)threadIdx.x + FT * (o >> 1)) + (o & 1); }
+// Position within the block of a thread's real output o: point j + T r of the inverse
+// transform holds outputs 2 (j + T r) (real part) and 2 (j + T r) + 1 (imaginary part),
+// o = 2 r + part.
+template <int M>
+__device__ __forceinline__ int out_pos(int o) {
+  return 2 * ((int)threadIdx.x + Plan<M>::T * (o >> 1)) + (o & 1);
+}
 
-// Spectrogram / spectrum flush of one f0 bin for this thread's outputs.
-template <int NO>
+// Spectrogram / spectrum flush of one f0 bin for this thread's 16 outputs (bit o of vmask:
+// output o is a valid offset of the series).
+template <int M>
 __device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p, int bin,
-                                          const float (&binmax)[NO], int64_t tau_base,
-                                          int valid, float scale) {
+                                          const float (&binmax)[16], int tau_base,
+                                          unsigned vmask, float scale) {
   unsigned long long fix = 0ull;
 #pragma unroll
-  for (int o = 0; o < NO; ++o) {
-    const int64_t tau = tau_base + out_pos(o);
-    if (out_pos(o) < valid && tau < sg.W) {
+  for (int o = 0; o < 16; ++o) {
+    if (vmask & (1u << o)) {
+      const int tau = tau_base + out_pos<M>(o);
       const double inv = sg.inv_norm[tau];
       if (inv > 0.0) {
-        const float s = (float)((double)binmax[o] * (double)scale * inv);
+        const float s = (float)((double)(binmax[o] * scale) * inv);
         if (sg.spec) {
-          const int64_t at = (int64_t)bin * sg.spec_rows + tau / p.t_block;
+          const int row = p.t_block == 1 ? tau : tau / p.t_block;
+          const int64_t at = (int64_t)bin * sg.spec_rows + row;
           if (p.t_block == 1)
             sg.spec[at] = s;
           else
@@ -288,15 +339,16 @@ __device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p,
 
 // The search: work item = (series, block, range of whole f0 bins), numbered range-fastest;
 // persistent over the batch's items.  Per template of the range: C = conj(H_k) X_b, the
-// inverse real FFT, and the running reductions of the valid outputs.
+// inverse real FFT, and the running reductions of the thread's 16 outputs.  The next
+// template's spectrum is loaded into registers while the current one is transformed.
 template <int M>
-__global__ __launch_bounds__(FT) void k_fft_main(const BatchHdr* __restrict__ hdr, BankDev b,
-                                                 SearchDev p) {
-  constexpr int R = LastRadix<M>::R;
-  constexpr int NO = 2 * R;             // real outputs per thread
-  constexpr int NP = (M / 2 + FT) / FT; // spectrum pairs per thread (M / 2 + 1 pairs)
+__global__ __launch_bounds__(Plan<M>::T, 4) void k_fft_main(const BatchHdr* __restrict__ hdr,
+                                                          BankDev b, SearchDev p) {
+  constexpr int T = Plan<M>::T;
+  constexpr int NP = (M / 2 + T) / T;   // spectrum pairs per thread (M / 2 + 1 pairs)
+  static_assert(T * 16 == 2 * M, "pairs are T apart: twiddles step by 1/16 of a turn");
   __shared__ float2 xs[M + 2];
-  __shared__ float2 buf[M];
+  __shared__ float2 buf[Padded<M>::n];
   const SegDesc* segs = hdr_segs(hdr);
   const float2* spectra = (const float2*)b.data;
   const int n_ranges = hdr->n_ranges;
@@ -306,13 +358,11 @@ __global__ __launch_bounds__(FT) void k_fft_main(const BatchHdr* __restrict__ hd
   const float scale = 1.0f / (float)M;
   const int nfd = b.n_fdot;
 
-  // post-processing twiddles exp(+2 pi i p / N) of this thread's spectrum pairs
-  float2 wp[NP];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    const int pp = tid + q * FT;
-    wp[q] = cis_rev<true>((float)(pp <= M / 2 ? pp : 0) / (float)(2 * M));
-  }
+  // per-thread constants: the post-processing twiddle exp(+2 pi i p / N) of pair
+  // p = tid + q T is wb * exp(2 pi i q / 16); the inverse passes' twiddle bases
+  const float2 wb = cis_rev<true>((float)tid / (float)(2 * M));
+  PassTw<M, true> tw;
+  tw.init();
 
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int rg = (int)(item % n_ranges);
@@ -324,65 +374,96 @@ __global__ __launch_bounds__(FT) void k_fft_main(const BatchHdr* __restrict__ hd
     }
     const SegDesc& sg = segs[lo];
     const int64_t blk = tt - sg.tile0;
-    const int64_t tau_base = blk * valid;
+    const int tau_base = (int)(blk * valid);     // series are shorter than 2^31 samples
     const int b_lo = (int)((int64_t)rg * b.n_bins / n_ranges);
     const int b_hi = (int)((int64_t)(rg + 1) * b.n_bins / n_ranges);
     const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
-    for (int k = tid; k <= M; k += FT) xs[k] = xsrc[k];
-    __syncthreads();
-
-    float best[NO], binmax[NO];
-    int bestk[NO];
+    for (int k = tid; k <= M; k += T) xs[k] = xsrc[k];
+    unsigned vmask = 0u;
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
+    for (int o = 0; o < 16; ++o)
+      if (out_pos<M>(o) < valid && (int64_t)tau_base + out_pos<M>(o) < sg.W) vmask |= 1u << o;
+
+    float best[16], binmax[16];
+    int bestk[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
       best[o] = -1.0f;
       bestk[o] = -1;
       binmax[o] = 0.0f;
     }
-    const int64_t k_lo = (int64_t)b_lo * nfd, k_hi = (int64_t)b_hi * nfd;
-    for (int64_t k = k_lo; k < k_hi; ++k) {
-      const float2* hk = spectra + k * (int64_t)(M + 2);
+    const int k_lo = b_lo * nfd, k_hi = b_hi * nfd;
+    // spectrum pairs (p, M - p) of the current template, loaded ahead
+    float2 h1[NP], h2[NP];
+    {
+      const float2* hk = spectra + (int64_t)k_lo * (M + 2);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int pp = tid + q * T;
+        if (pp <= M / 2) {
+          h1[q] = hk[pp];
+          h2[q] = hk[M - pp];
+        }
+      }
+    }
+    __syncthreads();   // xs filled
+    int bin = b_lo, left = nfd;
+    for (int k = k_lo; k < k_hi; ++k) {
       // Y[p] and Y[M - p] from C = conj(H) X at bins p and M - p
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const int pp = tid + q * FT;
+        const int pp = tid + q * T;
         if (pp <= M / 2) {
           const int p2 = M - pp;
-          const float2 c1 = cmul(cconj(hk[pp]), xs[pp]);
-          const float2 c2 = cmul(cconj(hk[p2]), xs[p2]);
+          const float2 c1 = cmul(cconj(h1[q]), xs[pp]);
+          const float2 c2 = cmul(cconj(h2[q]), xs[p2]);
           const float2 e = cscale(cadd(c1, cconj(c2)), 0.5f);
           const float2 d = cscale(csub(c1, cconj(c2)), 0.5f);
-          const float2 o = cmul(d, wp[q]);
-          buf[pp] = make_float2(e.x - o.y, e.y + o.x);                 // E + iO
-          if (pp != 0 && pp != M / 2) buf[p2] = make_float2(e.x + o.y, o.x - e.y);  // E* + iO*
+          const float2 w = q == 0 ? wb : cmul(wb, make_float2(C16[q], S16[q]));
+          const float2 o = cmul(d, w);
+          buf[pad(pp)] = make_float2(e.x - o.y, e.y + o.x);                 // E + iO
+          if (pp != 0 && pp != M / 2) buf[pad(p2)] = make_float2(e.x + o.y, o.x - e.y);  // E* + iO*
+        }
+      }
+      if (k + 1 < k_hi) {
+        const float2* hk = spectra + (int64_t)(k + 1) * (M + 2);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int pp = tid + q * T;
+          if (pp <= M / 2) {
+            h1[q] = hk[pp];
+            h2[q] = hk[M - pp];
+          }
         }
       }
       __syncthreads();
-      float2 y[R];
-      fft_run<M, true, true>(buf, y);
+      float2 y[8];
+      fft_run<M, true, true>(buf, tw, y);
       // running maxima over the templates, lowest k on ties (k increases, strict >)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int r = 0; r < 8; ++r) {
         const float a0 = fabsf(y[r].x), a1 = fabsf(y[r].y);
         const bool g0 = a0 > best[2 * r], g1 = a1 > best[2 * r + 1];
         best[2 * r] = g0 ? a0 : best[2 * r];
-        bestk[2 * r] = g0 ? (int)k : bestk[2 * r];
+        bestk[2 * r] = g0 ? k : bestk[2 * r];
         best[2 * r + 1] = g1 ? a1 : best[2 * r + 1];
-        bestk[2 * r + 1] = g1 ? (int)k : bestk[2 * r + 1];
+        bestk[2 * r + 1] = g1 ? k : bestk[2 * r + 1];
         binmax[2 * r] = fmaxf(binmax[2 * r], a0);
         binmax[2 * r + 1] = fmaxf(binmax[2 * r + 1], a1);
       }
-      if ((k + 1) % nfd == 0) {
-        fft_flush<NO>(sg, p, (int)(k / nfd), binmax, tau_base, valid, scale);
+      if (--left == 0) {
+        fft_flush<M>(sg, p, bin, binmax, tau_base, vmask, scale);
 #pragma unroll
-        for (int o = 0; o < NO; ++o) binmax[o] = 0.0f;
+        for (int o = 0; o < 16; ++o) binmax[o] = 0.0f;
+        ++bin;
+        left = nfd;
       }
     }
     // per-offset maxima: one packed atomic per valid output (value first, then lower k)
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
-      const int64_t tau = tau_base + out_pos(o);
-      if (out_pos(o) < valid && tau < sg.W && bestk[o] >= 0) {
+    for (int o = 0; o < 16; ++o) {
+      const int tau = tau_base + out_pos<M>(o);
+      if ((vmask & (1u << o)) && bestk[o] >= 0) {
         const unsigned int kg = (unsigned int)(b.k_offset + bestk[o]);
         const unsigned long long key =
             ((unsigned long long)__float_as_uint(best[o] * scale) << 32) |
@@ -397,7 +478,7 @@ __global__ __launch_bounds__(FT) void k_fft_main(const BatchHdr* __restrict__ hd
 template <int M>
 hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsigned* bad,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_bank<M>, dim3((unsigned)b.K_pad), dim3(FT), 0, s, g, b,
+  hipLaunchKernelGGL(k_fft_bank<M>, dim3((unsigned)b.K_pad), dim3(Plan<M>::T), 0, s, g, b,
                      (float2*)dst, bad);
   return hipGetLastError();
 }
@@ -405,10 +486,10 @@ hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsi
 template <int M>
 hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                const SearchDev& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(FT), 0, s, hdr, b);
+  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_main<M>, dim3((unsigned)blocks), dim3(FT), 0, s, hdr, b, p);
+  hipLaunchKernelGGL(k_fft_main<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b, p);
   return hipGetLastError();
 }
 
