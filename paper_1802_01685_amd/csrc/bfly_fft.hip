@@ -20,6 +20,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 namespace bfly {
 
 namespace {
@@ -341,9 +343,11 @@ __device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p,
 // persistent over the batch's items.  Per template of the range: C = conj(H_k) X_b, the
 // inverse real FFT, and the running reductions of the thread's 16 outputs.  The next
 // template's spectrum is loaded into registers while the current one is transformed.
-template <int M>
-__global__ __launch_bounds__(Plan<M>::T, 4) void k_fft_main(const BatchHdr* __restrict__ hdr,
-                                                          BankDev b, SearchDev p) {
+// OCC: waves per SIMD the register allocation targets (2: no spills in the template loop;
+// 4: two work-groups per CU at M = 4096, some spills).
+template <int M, int OCC>
+__global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __restrict__ hdr,
+                                                            BankDev b, SearchDev p) {
   constexpr int T = Plan<M>::T;
   constexpr int NP = (M / 2 + T) / T;   // spectrum pairs per thread (M / 2 + 1 pairs)
   static_assert(T * 16 == 2 * M, "pairs are T apart: twiddles step by 1/16 of a turn");
@@ -475,6 +479,16 @@ __global__ __launch_bounds__(Plan<M>::T, 4) void k_fft_main(const BatchHdr* __re
   }
 }
 
+// Register target of the search kernel: BF_FFT_OCC=4 selects the 4-waves-per-SIMD build
+// (a tuning knob; results do not depend on it), else 2.
+int fft_occupancy() {
+  static const int occ = [] {
+    const char* e = getenv("BF_FFT_OCC");
+    return (e && e[0] == '4') ? 4 : 2;
+  }();
+  return occ;
+}
+
 template <int M>
 hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsigned* bad,
                              hipStream_t s) {
@@ -489,7 +503,12 @@ hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDe
   hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_main<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b, p);
+  if (fft_occupancy() == 4)
+    hipLaunchKernelGGL((k_fft_main<M, 4>), dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr,
+                       b, p);
+  else
+    hipLaunchKernelGGL((k_fft_main<M, 2>), dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr,
+                       b, p);
   return hipGetLastError();
 }
 
