@@ -3,7 +3,8 @@
 Tolerances (max relative error of the butterfly output m and of the spectrogram S over
 non-degenerate offsets): FP32 1e-5, BF16 hi/lo split 1e-4, FP16 template split (fp16 data)
 1e-3 and FP8 (e4m3 with power-of-two template and strip scales) 0.2, the stated bounds of
-the last two.  Relative errors are taken
+those two; the FFT-correlation form (float32 spectra and transforms) 1e-5.  Relative errors
+are taken
 against max(value, 1/sqrt(L)).  Argmax: the template the GPU
 reports must reach the FP64 maximum within 2*tol (so it must be the oracle's template
 wherever the FP64 top-2 margin exceeds 2*tol*m).  Histograms: exact against the floor-rule
