@@ -99,7 +99,8 @@ def fft_roofline(res, p, bf):
     flops = res["K"] * blocks * (5.0 * m * math.log2(m) + 16.0 * m)
     achieved = flops / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": 157.3, "unit": "TFLOP/s",
-            "frac": round(achieved / 157.3, 4), "traffic": None, "kernel": "k_fft_data+k_fft_main",
+            "frac": round(achieved / 157.3, 4), "traffic": recorded_traffic("fft", "fft"),
+            "kernel": "k_fft_data+k_fft_main",
             "kernel_ms": round(ms, 3), "fft_points": 2 * m, "valid_per_block": valid}
 
 
@@ -249,7 +250,8 @@ def recorded_traffic(prec, tile):
     size), if it was taken on exactly the current kernel source and tile; else None."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_1802_01685_amd", "csrc", "bfly_kernels.hip")
+    kernel_file = "bfly_fft.hip" if prec == "fft" else "bfly_kernels.hip"
+    src = os.path.join(ROOT, "paper_1802_01685_amd", "csrc", kernel_file)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
@@ -288,7 +290,7 @@ def main() -> int:
                     help="search depth of the kappa-sigma tail leg (0 skips it)")
     ap.add_argument("--extra-forms", default="f16x2,fft",
                     help="comma-separated further precision forms to time and check ('' skips)")
-    ap.add_argument("--cpu-offsets", type=int, default=1024, help="0 skips the oracle leg")
+    ap.add_argument("--cpu-offsets", type=int, default=3072, help="0 skips the oracle leg")
     ap.add_argument("--serve-segments", type=int, default=16,
                     help="segments per point of the serving leg (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

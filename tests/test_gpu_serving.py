@@ -67,7 +67,7 @@ def _same(a, b, label):
             (label, k)
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "fft"])
 def test_alone_equals_mix_equals_direct(bf, prec):
     bank = bf.bank_create(P, prec)
     prm = bf.make_params(t_block=4, hist_bins=64)
