@@ -166,7 +166,7 @@ def tails_leg(bf, torch, p, xs, prec, kappa, steps):
     counts = [t["bin_counts"].cpu().numpy().view("uint32").astype("int64") for t in tails]
     sig = tails[0]["sigma"].cpu().numpy()
     res = {"kappa": kappa, "precision_form": prec, "ms_per_step": wall / steps * 1e3,
-           "correlations_per_s": corr * steps / wall, "passes": 2,
+           "correlations_per_s": corr * steps / wall, "passes": 3 if prec == "fft" else 2,
            "n_tails": n_tails, "tail_counts_total": [int(c.sum()) for c in counts],
            "sigma_median_x_sqrtL": float(np.median(sig) * np.sqrt(p.L)),
            "series": ["data", "control"][:len(xs)]}
@@ -343,9 +343,11 @@ def main() -> int:
 
     tails = None
     if args.tails_kappa > 0:
-        log(f"tails leg: kappa = {args.tails_kappa}, {args.precision}, 1 + 2 runs")
-        tails = tails_leg(bf, torch, p, xs, args.precision, args.tails_kappa, 2)
-        log(f"  {tails}")
+        tails = {}
+        for form in dict.fromkeys([args.precision, "fft"]):
+            log(f"tails leg: kappa = {args.tails_kappa}, {form}, 1 + 2 runs")
+            tails[form] = tails_leg(bf, torch, p, xs, form, args.tails_kappa, 2)
+            log(f"  {tails[form]}")
 
     cpu = None
     err = {}

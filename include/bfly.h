@@ -71,7 +71,7 @@ typedef enum {
                     1e-3 */
   BF_FFT = 4     /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
                     real FFTs of length N = the smallest power of two >= max(2L, 1024);
-                    L <= 4096; same outputs as the direct forms (no tails) */
+                    L <= 4096; the same outputs as the direct forms */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;
@@ -209,8 +209,10 @@ bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_
 
 /* The search of bf_search_batch plus the kappa-sigma tails of every series: the
  * contraction runs twice on the stream (the first pass also sums rho^2 per template, the
- * second extracts the tails against kappa * sigma_k).  kappa finite and >= 0; sigma,
- * bin_counts and n_tails are required.  segs is a host array. */
+ * second extracts the tails against kappa * sigma_k); with an FFT bank the search, the
+ * rho^2 sums and the extraction are three passes of the FFT kernel over the data spectra.
+ * kappa finite and >= 0; sigma, bin_counts and n_tails are required.  segs is a host
+ * array. */
 bf_status bf_search_tails(const bf_bank* bank, const bf_tail_segment* segs, int32_t n_segs,
                           float kappa, const bf_search_params* params, void* workspace,
                           size_t workspace_bytes, bf_stream stream);

@@ -250,8 +250,6 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
   }
   const bool with_tails = tails != nullptr;
-  if (with_tails && b.precision == P_FFT)
-    return fail(BF_EINVAL, "the tail search needs a direct-contraction bank, not the FFT form");
   if (with_tails && !(kappa >= 0.0f && std::isfinite(kappa)))
     return fail(BF_EINVAL, "kappa must be finite and >= 0");
   size_t need = table_bytes(n_segs);
@@ -284,7 +282,9 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     }
   }
 
-  const SearchDev sp = make_search(b, prm, with_tails ? MODE_SIGMA : MODE_SEARCH, kappa);
+  // the FFT form's search pass is a plain search; its sigma pass comes after
+  const SearchDev sp = make_search(b, prm, with_tails && b.precision != P_FFT ? MODE_SIGMA
+                                                                           : MODE_SEARCH, kappa);
   std::vector<SeriesBufs> sb((size_t)n_segs);
   char* ws = (char*)workspace;
   size_t off = table_bytes(n_segs);
@@ -322,7 +322,7 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   if (!with_tails) return enqueue_kernels(b, sp, tab_dev, n_segs, xb, ti.n_items, stream, te);
   SearchDev sp_t = sp;
   sp_t.mode = MODE_TAILS;
-  HIP_TRY(prepare_main(b, sp_t), "hipFuncSetAttribute(k_main)");
+  if (b.precision != P_FFT) HIP_TRY(prepare_main(b, sp_t), "hipFuncSetAttribute(k_main)");
   return enqueue_tail_kernels(b, sp, sp_t, tab_dev, n_segs, xb, ti.n_items, stream, te);
 }
 
@@ -569,6 +569,15 @@ bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
   bf_status st = enqueue_kernels(b, sp_sigma, table_dev, seg_slots, x_blocks, main_blocks,
                                  stream, te);
   if (st != BF_OK) return st;
+  if (b.precision == P_FFT) {
+    // the FFT form: a sigma pass and a tails pass over the search's data spectra
+    SearchDev s1 = sp_tails;
+    s1.mode = MODE_SIGMA;
+    HIP_TRY(launch_fft_pass(table_dev, main_blocks, b, s1, stream), "k_fft sigma launch");
+    HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
+    HIP_TRY(launch_fft_pass(table_dev, main_blocks, b, sp_tails, stream), "k_fft tails launch");
+    return BF_OK;
+  }
   HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
   HIP_TRY(launch_main(table_dev, main_blocks, b, sp_tails, stream), "k_main launch");
   return BF_OK;

@@ -345,7 +345,11 @@ __device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p,
 // template's spectrum is loaded into registers while the current one is transformed.
 // OCC: waves per SIMD the register allocation targets (2: no spills in the template loop;
 // 4: two work-groups per CU at M = 4096, some spills).
-template <int M, int OCC>
+// MODE (MainMode): the search; the pass that sums rho^2 per template (fixed point, one
+// atomic per wave and template); the pass that appends every valid (tau, k) with
+// |rho| > kappa sigma_k and counts it per bin.  rho = f32(d / sqrt(E)) as in the direct
+// forms' tail passes.
+template <int M, int OCC, int MODE>
 __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __restrict__ hdr,
                                                             BankDev b, SearchDev p) {
   constexpr int T = Plan<M>::T;
@@ -390,11 +394,16 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
 
     float best[16], binmax[16];
     int bestk[16];
+    float inv[16];     // sigma and tails passes: 1/sqrt(E) of the outputs (0 if not valid)
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
-      best[o] = -1.0f;
-      bestk[o] = -1;
-      binmax[o] = 0.0f;
+      if constexpr (MODE == MODE_SEARCH) {
+        best[o] = -1.0f;
+        bestk[o] = -1;
+        binmax[o] = 0.0f;
+      } else {
+        inv[o] = (vmask & (1u << o)) ? (float)sg.inv_norm[tau_base + out_pos<M>(o)] : 0.0f;
+      }
     }
     const int k_lo = b_lo * nfd, k_hi = b_hi * nfd;
     // spectrum pairs (p, M - p) of the current template, loaded ahead
@@ -443,6 +452,43 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
       __syncthreads();
       float2 y[8];
       fft_run<M, true, true>(buf, tw, y);
+      if constexpr (MODE == MODE_SIGMA) {
+        float q = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const float r0 = (float)((double)(y[r].x * scale) * (double)inv[2 * r]);
+          const float r1 = (float)((double)(y[r].y * scale) * (double)inv[2 * r + 1]);
+          q = fmaf(r0, r0, q);
+          q = fmaf(r1, r1, q);
+        }
+        unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const unsigned lo = __shfl_xor((unsigned)(f & 0xFFFFFFFFull), o, 64);
+          const unsigned hi = __shfl_xor((unsigned)(f >> 32), o, 64);
+          f += ((unsigned long long)hi << 32) | lo;
+        }
+        if ((tid & 63) == 0 && f != 0ull) atomicAdd(sg.sig_acc + k, f);
+        continue;
+      }
+      if constexpr (MODE == MODE_TAILS) {
+        const float thr = sg.thr[k];
+#pragma unroll
+        for (int o = 0; o < 16; ++o) {
+          const float v = (o & 1) ? y[o >> 1].y : y[o >> 1].x;
+          const float rf = (float)((double)(v * scale) * (double)inv[o]);
+          if (fabsf(rf) > thr) {
+            const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
+            if ((int64_t)slot < sg.tail_cap) {
+              sg.t_tau[slot] = tau_base + out_pos<M>(o);
+              sg.t_k[slot] = (int32_t)(b.k_offset + k);
+              sg.t_rho[slot] = rf;
+            }
+            atomicAdd(sg.t_bins + k / nfd, 1u);
+          }
+        }
+        continue;
+      }
       // running maxima over the templates, lowest k on ties (k increases, strict >)
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -467,7 +513,7 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
       const int tau = tau_base + out_pos<M>(o);
-      if ((vmask & (1u << o)) && bestk[o] >= 0) {
+      if (MODE == MODE_SEARCH && (vmask & (1u << o)) && bestk[o] >= 0) {
         const unsigned int kg = (unsigned int)(b.k_offset + bestk[o]);
         const unsigned long long key =
             ((unsigned long long)__float_as_uint(best[o] * scale) << 32) |
@@ -504,11 +550,26 @@ hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDe
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (fft_occupancy() == 4)
-    hipLaunchKernelGGL((k_fft_main<M, 4>), dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr,
-                       b, p);
+    hipLaunchKernelGGL((k_fft_main<M, 4, MODE_SEARCH>), dim3((unsigned)blocks),
+                       dim3(Plan<M>::T), 0, s, hdr, b, p);
   else
-    hipLaunchKernelGGL((k_fft_main<M, 2>), dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr,
-                       b, p);
+    hipLaunchKernelGGL((k_fft_main<M, 2, MODE_SEARCH>), dim3((unsigned)blocks),
+                       dim3(Plan<M>::T), 0, s, hdr, b, p);
+  return hipGetLastError();
+}
+
+// The sigma or tails pass (p.mode) over the data spectra the search left in the workspace.
+template <int M>
+hipError_t launch_fft_pass_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                             const SearchDev& p, hipStream_t s) {
+  if (p.mode == MODE_SIGMA)
+    hipLaunchKernelGGL((k_fft_main<M, 2, MODE_SIGMA>), dim3((unsigned)blocks),
+                       dim3(Plan<M>::T), 0, s, hdr, b, p);
+  else if (p.mode == MODE_TAILS)
+    hipLaunchKernelGGL((k_fft_main<M, 2, MODE_TAILS>), dim3((unsigned)blocks),
+                       dim3(Plan<M>::T), 0, s, hdr, b, p);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -536,6 +597,12 @@ hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev&
                              const SearchDev& p, hipStream_t s) {
   if (blocks < 1) return hipSuccess;
   BFLY_FFT_DISPATCH(launch_fft_search_t, hdr, blocks, b, p, s);
+}
+
+hipError_t launch_fft_pass(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                           const SearchDev& p, hipStream_t s) {
+  if (blocks < 1) return hipSuccess;
+  BFLY_FFT_DISPATCH(launch_fft_pass_t, hdr, blocks, b, p, s);
 }
 
 }  // namespace bfly

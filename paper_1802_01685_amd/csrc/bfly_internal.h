@@ -164,6 +164,9 @@ size_t main_lds_bytes(int precision, int L_pad, int n_wg);
 hipError_t launch_fft_bank(const GridDev& g, const BankDev& b, void* dst, hipStream_t s);
 hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                              const SearchDev& p, hipStream_t s);
+// The sigma or tails pass of a tail search (p.mode), after the search left the data spectra.
+hipError_t launch_fft_pass(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                           const SearchDev& p, hipStream_t s);
 
 // Two-detector coincidence (bfly_coinc.hip).  A channel's tail list (device) and its output
 // counts per f0 bin; the workspace of the offset buckets of channel B.

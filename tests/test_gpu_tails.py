@@ -20,7 +20,7 @@ from synth import BankParams, bank_params, cfg1_series, time_randomised, white_n
 from tests.parity_util import TOL, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-PRECS = ["fp32", "bf16x3", "f16x2", "fp8"]
+PRECS = ["fp32", "bf16x3", "f16x2", "fp8", "fft"]
 
 SMALL = BankParams(fs=128.0, L=48, n_f0=5, n_fdot=7, f0_min=3.0, f0_max=40.0,
                    fdot_min=-30.0, fdot_max=25.0)
@@ -120,7 +120,7 @@ def test_tails_small_with_edges(bf, prec):
         assert np.array_equal(plain[key].view(np.uint8), outs[0][key].view(np.uint8)), key
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fft"])
 def test_tails_cfg1(bf, prec):
     """4 s at 512 Hz with a chirp, bank 16 x 16, L = 512, kappa = 4: every offset."""
     p = bank_params(1)
@@ -192,7 +192,7 @@ def _coinc_np(c: dict) -> dict:
             "n_pairs": int(c["n_pairs"].cpu().numpy()[0])}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fft"])
 def test_coincidence_two_channels(bf, prec):
     """Two simultaneous channels (independent noise, one common chirp at sample 1500):
     the GPU's coincidence counts equal the oracle's on the GPU's own tail lists, exactly,
