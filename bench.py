@@ -91,9 +91,11 @@ def fft_roofline(res, p, bf):
     real-FFT post-processing (~16 M flop)."""
     import math
     ms = res["kernel_ms"]["main"]
-    m = 512
-    while 2 * m < 2 * p.L:
-        m *= 2
+    m, best = 512, 1e300
+    for mm, lg in ((512, 9), (1024, 10), (2048, 11), (4096, 12)):   # as the library picks N
+        v = 2 * mm - p.L + 1
+        if v >= 1 and mm * lg / v < best * 0.999:
+            m, best = mm, mm * lg / v
     valid = 2 * m - p.L + 1
     blocks = sum(-(-w // valid) for w in res["W"])
     flops = res["K"] * blocks * (5.0 * m * math.log2(m) + 16.0 * m)
@@ -290,7 +292,7 @@ def main() -> int:
                     help="search depth of the kappa-sigma tail leg (0 skips it)")
     ap.add_argument("--extra-forms", default="f16x2,fft",
                     help="comma-separated further precision forms to time and check ('' skips)")
-    ap.add_argument("--cpu-offsets", type=int, default=3072, help="0 skips the oracle leg")
+    ap.add_argument("--cpu-offsets", type=int, default=8192, help="0 skips the oracle leg")
     ap.add_argument("--serve-segments", type=int, default=16,
                     help="segments per point of the serving leg (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

@@ -70,8 +70,8 @@ typedef enum {
                     rounding bounds the error: ~1e-4 to 7e-4 relative, stated bound
                     1e-3 */
   BF_FFT = 4     /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
-                    real FFTs of length N = the smallest power of two >= max(2L, 1024);
-                    L <= 4096; the same outputs as the direct forms */
+                    real FFTs of length N = 2M, M in 512..4096 minimising M log2 M per valid
+                    output (N - L + 1); L <= 4096; the same outputs as the direct forms */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;

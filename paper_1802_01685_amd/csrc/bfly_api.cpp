@@ -110,10 +110,19 @@ void fill_geometry(const bf_bank_desc* d, GridDev* g, BankDev* b) {
   b->precision = d->precision;
   b->fft_m = 0;
   if (d->precision == BF_FFT) {
-    // real FFT length N = the smallest power of two >= 2L (at least 1024), M = N / 2
-    int32_t m = 512;
-    while (2 * m < 2 * d->L) m *= 2;
-    b->fft_m = m;
+    // real FFT length N = 2M, M in 512..4096: the one with the least transform work per
+    // valid output, M log2 M / (2M - L + 1) (e.g. N = 8192 for L = 2000 or 4096, 4096 for
+    // L = 512)
+    double best = 1e300;
+    for (int32_t m = 512, lg = 9; m <= 4096; m *= 2, ++lg) {
+      const int32_t valid = 2 * m - d->L + 1;
+      if (valid < 1) continue;
+      const double cost = (double)m * lg / (double)valid;
+      if (cost < best * 0.999) {
+        best = cost;
+        b->fft_m = m;
+      }
+    }
   }
 }
 
