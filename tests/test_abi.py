@@ -68,3 +68,29 @@ def test_bank_bytes_and_validation_on_host(lib):
             lib.bank_bytes(q)
         assert e.value.status == lib.BF_EINVAL
         assert lib.last_error() != ""
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The binding has no fallback: with the shared library absent it raises, and no module
+    of the package imports the oracle."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import sys\n"
+        "from paper_1802_01685_amd import bfly\n"
+        f"bfly.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "bfly._lib = None\n"
+        "try:\n"
+        "    bfly.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(1)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True)
+    assert r.returncode == 0 and "raised" in r.stdout, r.stdout + r.stderr
+    pkg = os.path.join(root, "paper_1802_01685_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            assert "oracle" not in open(os.path.join(pkg, name)).read(), name
