@@ -364,10 +364,15 @@ def main() -> int:
         log(f"  oracle {cpu['value']:.4g} corr/s on {cpu['cores']} threads; errors {err}")
 
     serving = None
+    serving_other = {}
     if args.serve_segments > 0:
         log(f"serving leg: {args.serve_segments} segments per point")
         serving = serving_leg(bf, args.precision, args.serve_segments, 32, 16)
         log(f"  {serving}")
+        if args.precision != "fft" and "fft" in args.extra_forms.split(","):
+            log("serving leg on the FFT form")
+            serving_other["fft"] = serving_leg(bf, "fft", args.serve_segments, 32, 16)
+            log(f"  {serving_other['fft']}")
 
     steps_ms = main_res["step_ms"]
     lat = serving["at_70pct_capacity"] if serving else None
@@ -411,6 +416,7 @@ def main() -> int:
         "error_vs_fp64": err or None,
         "cpu_baseline": cpu,
         "serving": serving,
+        "serving_other_forms": serving_other or None,
     }
     print(json.dumps(rec), flush=True)
     return 0

@@ -94,3 +94,48 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     for name in os.listdir(pkg):
         if name.endswith(".py"):
             assert "oracle" not in open(os.path.join(pkg, name)).read(), name
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include "bfly.h"
+
+int main(void) {
+  bf_bank_desc d = {0};
+  d.fs = 4096.0; d.L = 4096; d.n_f0 = 256; d.n_fdot = 256;
+  d.shard_index = 0; d.shard_count = 1; d.precision = BF_BF16X3;
+  d.f0_min = 50.0; d.f0_max = 2000.0; d.fdot_min = -2000.0; d.fdot_max = 2000.0;
+  size_t bytes = 0;
+  if (bf_bank_bytes(&d, &bytes) != BF_OK) return 2;
+  d.L = 0;
+  size_t ignored = 0;
+  const bf_status st = bf_bank_bytes(&d, &ignored);
+  printf("%zu %d %s\n", bytes, (int)st, bf_last_error());
+  return st == BF_EINVAL ? 0 : 3;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(lib, tmp_path):
+    """A C99 program includes bfly.h, links libbfly.so and calls host-side entry points."""
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    libdir = os.path.join(root, "paper_1802_01685_amd")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"),
+                        str(src), "-L", libdir, "-lbfly", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    if r.returncode != 0 and "-lbfly" in r.stderr:
+        pytest.skip("libbfly.so is not built")
+    assert r.returncode == 0, r.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert run.returncode == 0, run.stdout + run.stderr
+    bytes_, status = run.stdout.split()[:2]
+    assert int(bytes_) == 65536 * 4096 * 4 + 256 and int(status) == lib.BF_EINVAL
