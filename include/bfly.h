@@ -69,9 +69,15 @@ typedef enum {
                     scale; h_hi*x + h_lo*x (two MFMA products per tap).  The data's fp16
                     rounding bounds the error: ~1e-4 to 7e-4 relative, stated bound
                     1e-3 */
-  BF_FFT = 4     /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
+  BF_FFT = 4,    /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
                     real FFTs of length N = 2M, M in 512..4096 minimising M log2 M per valid
                     output (N - L + 1); L <= 4096; the same outputs as the direct forms */
+  BF_F16F8 = 5   /* fp16 product of the fp16-rounded template and data, plus the two residual
+                    products (template residual x data, template x data residual) as e4m3 codes
+                    with power-of-two scales (per template, per strip) undone by the MFMA scale
+                    operands; the rounded templates' sums times the window mean are
+                    subtracted.  Two thirds of BF_BF16X3's MFMA time per tap; ~1e-5 to 3e-5
+                    relative error, stated bound 1e-4; L <= 5248 */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;

@@ -67,10 +67,12 @@ bf_status check_desc(const bf_bank_desc* d) {
       d->shard_count > d->n_f0)
     return fail(BF_EINVAL, "need 0 <= shard_index < shard_count <= n_f0");
   if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8 &&
-      d->precision != BF_F16X2 && d->precision != BF_FFT)
+      d->precision != BF_F16X2 && d->precision != BF_FFT && d->precision != BF_F16F8)
     return fail(BF_EINVAL, "precision %d is not available", d->precision);
   if (d->precision == BF_FFT && d->L > MAX_FFT_L)
     return fail(BF_EINVAL, "the FFT form needs L <= %d", MAX_FFT_L);
+  if (d->precision == BF_F16F8 && d->L > MAX_F16F8_L)
+    return fail(BF_EINVAL, "the F16F8 form needs L <= %d", MAX_F16F8_L);
   const double v[4] = {d->f0_min, d->f0_max, d->fdot_min, d->fdot_max};
   for (double x : v)
     if (!std::isfinite(x)) return fail(BF_EINVAL, "grid bounds must be finite");
@@ -206,21 +208,22 @@ void release_staging(Staging* s, bool recorded) {
 int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
 // Tile shape of the contraction kernel: tm template blocks x tn offset blocks (of 32) per
-// wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i] (e.g. "2x8i", i = interleaved)
-// overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
+// wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i|p] (e.g. "2x8i"; i = interleaved,
+// p = split-phase) overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
 // depend on it (FP8 does, through its per-strip scales).
 void choose_tile(int precision, int mode, int32_t* tm, int32_t* tn, int32_t* pipe) {
   // Defaults from measurement on MI355X: the split forms are fastest with 2 x 8 blocks and
   // the interleaved schedule; FP32 (64-cycle MFMAs) and FP8 with 2 x 4.
+  // F16F8 has one shape, 2 x 8 with its split-phase schedule.
   const bool split = precision == BF_BF16X3 || precision == BF_F16X2;
   *tm = 2;
-  *tn = split ? 8 : 4;
-  *pipe = split ? 1 : 0;
+  *tn = split || precision == BF_F16F8 ? 8 : 4;
+  *pipe = split ? 1 : precision == BF_F16F8 ? 2 : 0;
   const char* e = getenv("BF_TILE");
   int a = 0, c = 0;
   char il = 0;
   if (e && sscanf(e, "%dx%d%c", &a, &c, &il) >= 2) {
-    const int pp = il == 'i' ? 1 : 0;
+    const int pp = il == 'i' ? 1 : il == 'p' ? 2 : 0;
     if (main_variant_exists(precision, a, c, pp, mode)) {
       *tm = a;
       *tn = c;
@@ -647,7 +650,7 @@ bf_status bf_bank_create(const bf_bank_desc* desc, void* dev_mem, size_t dev_byt
     bk->grid = g;
     bk->dev = b;
     bk->dev.data = dev_mem;
-    if (b.precision == P_FP8) {
+    if (has_side_tables(b.precision)) {
       bk->dev.texp = (const int32_t*)((char*)dev_mem + bank_data_bytes(b));
       bk->dev.tsum = (const float*)(bk->dev.texp + b.K_pad);
     }

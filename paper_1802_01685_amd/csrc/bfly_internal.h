@@ -18,20 +18,35 @@ constexpr int TILE_K = 64;                    // K_pad granule (largest template
 constexpr int MAX_N_WG = 32 * 8 * WG_WAVES;  // offsets per work item at tn = 8
 constexpr int KCH = 16;                       // taps per chunk, FP32 and BF16 forms
 constexpr int KCH_FP8 = 64;                   // taps per chunk, FP8 form
+constexpr int KCH_F16F8 = 32;                 // taps per chunk, F16F8 form
 constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG + L_pad
 constexpr int MAX_L = 8192;
 constexpr int MAX_FFT_L = 4096;              // FFT form: N = 2M <= 8192
+constexpr int MAX_F16F8_L = 5248;            // F16F8: 24-byte strip cells + 12 KB fill 160 KB LDS
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
 constexpr double SIGMA_FIX_SCALE = 68719476736.0;   // 2^36: fixed-point sums of rho^2
 
-enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4 };
+enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4, P_F16F8 = 5 };
 
-// F16X2: templates are stored as fp16 hi + lo of h * 2^F16_TEMPLATE_EXP.
+// F16X2 and F16F8: templates are stored as fp16 (hi + lo) of h * 2^F16_TEMPLATE_EXP.
 constexpr int F16_TEMPLATE_EXP = 10;
 
+// F16F8: the e4m3 codes of the template residual are scaled by 2^(e_k + F8_LO_SHIFT), those
+// of the data residual by 2^F8_XLO_EXP, and those of the fp16 strip samples by
+// 2^-F8_XHI_SHIFT; with these the two correction products share one scale (see k_main).
+constexpr int F8_LO_SHIFT = 11;
+constexpr int F8_XLO_EXP = 5;
+constexpr int F8_XHI_SHIFT = 6;
+
 // Taps per K-loop chunk; L_pad is a multiple of twice this.
-constexpr int chunk_taps(int precision) { return precision == P_FP8 ? KCH_FP8 : KCH; }
+constexpr int chunk_taps(int precision) {
+  return precision == P_FP8 ? KCH_FP8 : precision == P_F16F8 ? KCH_F16F8 : KCH;
+}
+// Forms whose bank carries per-template exponents and template sums.
+constexpr bool has_side_tables(int precision) {
+  return precision == P_FP8 || precision == P_F16F8;
+}
 
 // Per-series table entry, resident in the workspace (device).
 struct SegDesc {
@@ -85,8 +100,9 @@ __host__ __device__ inline const SegDesc* hdr_segs(const BatchHdr* h) {
 // The bank as the kernels see it (passed by value).
 struct BankDev {
   const void* data;     // tile layout, see bank_gen
-  const int32_t* texp;  // FP8: per-template power-of-two exponent e_k (codes hold h * 2^e_k)
-  const float* tsum;    // FP8: sum over taps of the dequantised template (not exactly 0)
+  const int32_t* texp;  // FP8, F16F8: per-template power-of-two exponent e_k (codes hold
+                        // h * 2^e_k)
+  const float* tsum;    // FP8, F16F8: sum over taps of the rounded template (not exactly 0)
   int64_t K;            // local templates
   int64_t K_pad;        // multiple of TILE_K
   int64_t k_offset;     // global index of local template 0
@@ -122,16 +138,16 @@ struct SearchDev {
 // that extracts the tails above kappa * sigma_k (and does nothing else).
 enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2 };
 
-// Bytes of the quantised templates, of the FP8 exponents, and of the whole bank allocation
-// (templates, exponents, then a 256-byte status word).
+// Bytes of the quantised templates, of the per-template side tables, and of the whole bank
+// allocation (templates, side tables, then a 256-byte status word).
 inline size_t bank_data_bytes(const BankDev& b) {
   if (b.precision == P_FFT) return (size_t)b.K_pad * (size_t)(b.fft_m + 2) * 8;  // spectra
   return (size_t)b.K_pad * (size_t)b.L_pad * (b.precision == P_FP8 ? 1 : 4);
 }
-// FP8 side tables after the codes: int32 exponent e_k [K_pad], then float sum of the
-// dequantised template [K_pad].
+// FP8 and F16F8 side tables after the codes: int32 exponent e_k [K_pad], then the float sum
+// of the rounded template [K_pad].
 inline size_t bank_exp_bytes(const BankDev& b) {
-  return b.precision == P_FP8 ? (((size_t)b.K_pad * 8 + 255) & ~(size_t)255) : 0;
+  return has_side_tables(b.precision) ? (((size_t)b.K_pad * 8 + 255) & ~(size_t)255) : 0;
 }
 inline size_t bank_total_bytes(const BankDev& b) {
   return bank_data_bytes(b) + bank_exp_bytes(b) + 256;

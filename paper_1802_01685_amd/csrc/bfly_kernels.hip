@@ -95,6 +95,14 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 //   largest exponent keeping max |h_k| * 2^e_k <= 448, and e_k is kept in texp[k].  The
 //   rounded template no longer sums to zero; that sum (in template units) is kept in
 //   tsum[k] so the contraction can remove the window mean's share of it.
+// F16F8 layout, per (b, 32-tap chunk c): four planes of 64 lanes x 16 bytes.  Planes 0 and 1
+//   are fp16 of h * 2^10, lane h*32 + m holding taps 32c + 16q + 8h + i (i < 8) of template
+//   32b + m -- the A operands of two v_mfma_f32_32x32x16_f16 steps.  Planes 2 and 3 hold the
+//   A operand of one v_mfma_scale_f32_32x32x64_f8f6f4 over the same 32 taps: lane m carries
+//   the e4m3 codes of the residual r = h - fp16(h * 2^10) * 2^-10 scaled by 2^(e_k + 11),
+//   lane 32 + m those of h scaled by 2^e_k (codes i < 16 in plane 2, the rest in plane 3).
+//   texp[k] = e_k as for FP8; tsum[k] is the sum of fp16(h * 2^10) * 2^-10 plus the rounded
+//   residual, the template that multiplies the data's fp16 part.
 // Padding templates (k >= K) and padding taps (n >= L) are zero.  The word after the bank
 // counts templates whose centred norm vanished (they cannot be normalised).
 // ---------------------------------------------------------------------------------------
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
   const int m = (int)(k & 31);
   int e8 = 0;
   double qsum = 0.0;   // FP8: sum of the stored codes, in units of 2^-e8
-  if (b.precision == P_FP8) {
+  if (has_side_tables(b.precision)) {
     double mx = 0.0;
     if (real)
       for (int n = lane; n < b.L; n += 64)
@@ -171,6 +179,22 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
       const int64_t base = ((int64_t)blk * b.n_chunks + c) * 2;
       out[((base + 0) * 64 + ln) * 8 + i] = hi;
       out[((base + 1) * 64 + ln) * 8 + i] = lo;
+    } else if (b.precision == P_F16F8) {
+      const int c = n >> 5, r = n & 31;
+      const _Float16 t16 = (_Float16)ldexp(h, F16_TEMPLATE_EXP);
+      const double rr = h - ldexp((double)t16, -F16_TEMPLATE_EXP);
+      // |rr| <= 2^-11 |h| (fp16 rounding), so both codes stay within 448
+      const float vl = (float)ldexp(rr, e8 + F8_LO_SHIFT);
+      const float vh = (float)ldexp(h, e8);
+      const int cl = __builtin_amdgcn_cvt_pk_fp8_f32(vl, 0.0f, 0, false) & 0xFF;
+      const int ch = __builtin_amdgcn_cvt_pk_fp8_f32(vh, 0.0f, 0, false) & 0xFF;
+      qsum += ldexp((double)t16, e8 - F16_TEMPLATE_EXP) +
+              ldexp((double)__builtin_amdgcn_cvt_f32_fp8(cl, 0), -F8_LO_SHIFT);
+      char* cbase = (char*)dst + ((int64_t)blk * b.n_chunks + c) * 4096;
+      const int q = r >> 4, hh = (r >> 3) & 1, i = r & 7;
+      *(_Float16*)(cbase + q * 1024 + (hh * 32 + m) * 16 + i * 2) = t16;
+      cbase[(2 + q) * 1024 + m * 16 + (r & 15)] = (char)cl;
+      cbase[(2 + q) * 1024 + (32 + m) * 16 + (r & 15)] = (char)ch;
     } else {
       const int c = n >> 6, r = n & 63;
       const int ln = (r >> 5) * 32 + m, i = r & 31;
@@ -181,7 +205,7 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
       out[(((int64_t)blk * b.n_chunks + c) * 64 + ln) * 32 + i] = (uint8_t)code;
     }
   }
-  if (b.precision == P_FP8) {
+  if (has_side_tables(b.precision)) {
     qsum = wave_sum_d(qsum);
     if (lane == 0) ((float*)(texp + b.K_pad))[k] = (float)ldexp(qsum, -e8);
   }
@@ -372,10 +396,18 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 //         x[tau + kk + 8h + i].  The strip is kept as four copies shifted by 0..3 samples,
 //         interleaved per 4-sample cell, so every lane's 8 consecutive samples are two
 //         8-byte-aligned LDS reads whatever tau is.  hi*hi + hi*lo + lo*hi are accumulated.
+//   F16F8 per 32-tap chunk: two v_mfma_f32_32x32x16_f16 steps as above (fp16 strip, one
+//         plane, four shifted copies) and one v_mfma_scale_f32_32x32x64_f8f6f4 whose K axis
+//         holds the two residual products over the same 32 taps: lanes h = 0 pair the
+//         template residual with the fp16 data, lanes h = 1 the template with the data
+//         residual.  Each of the two e4m3 strip planes keeps eight shifted copies.
 //   Output lane holds column n, rows 8g + 4h + i4 (g, i4 < 4) in accumulator 4g + i4.
 // ---------------------------------------------------------------------------------------
 size_t main_lds_bytes(int precision, int L_pad, int n_wg) {
   const size_t S = (size_t)n_wg + (size_t)L_pad + STRIP_SLACK;
+  // F16F8: fp16 plane + two e4m3 planes, then the item's 1/sqrt(E) (double) and window
+  // means (float)
+  if (precision == P_F16F8) return S * 24 + (size_t)n_wg * 12;
   return precision == P_FP32 ? S * 4 : (precision == P_FP8 || precision == P_F16X2) ? S * 8 : S * 16;
 }
 
@@ -569,6 +601,129 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[MB][NB], const AFrag<PRE
   }
 }
 
+// F16F8 fragments.  Template planes q0, q0 + 1 of chunk c (q0 = 0: the fp16 steps, q0 = 2:
+// the e4m3 step).
+template <int MB>
+__device__ __forceinline__ void f16f8_load_a(uint4 (&v)[MB][2], const void* bank, int64_t blk0,
+                                             int c, int nchunks, int lane, int q0) {
+  const uint4* A = (const uint4*)bank;
+#pragma unroll
+  for (int t = 0; t < MB; ++t) {
+    const int64_t idx = (((blk0 + t) * nchunks + c) * 4 + q0) * 64 + lane;
+    v[t][0] = A[idx];
+    v[t][1] = A[idx + 64];
+  }
+}
+
+// Strip fragments of an offset-block pair (blocks 2p, 2p + 1) for chunk c.  fp16 plane at
+// lds[0] (8 samples from x[tau + 32c + 16s + 8h], two 8-byte reads of the 4-copy layout, per
+// 16-tap step s); e4m3 planes after it (32 codes from x[tau + 32c], lanes h = 0 from the plane
+// of the fp16 samples, h = 1 from that of the residuals; four reads of the 8-copy layout).
+struct F16F8Pair {
+  uint4 h[2][2];   // [block of the pair][16-tap step]
+  uint4 e[2][2];   // [block of the pair][16 codes]
+};
+
+__device__ __forceinline__ void f16f8_load_pair(F16F8Pair& f, const char* lds, int off_w, int c,
+                                                int p, int n, int h, int plane_bytes) {
+  const int b16 = 8 * (off_w + n + 8 * h + 32 * c) + 512 * p;
+  const int b8 = plane_bytes * (1 + h) + 8 * (off_w + n + 32 * c) + 512 * p;
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int addr = b16 + 256 * jj + 128 * st;
+      const uint2 u0 = *(const uint2*)(lds + addr);
+      const uint2 u1 = *(const uint2*)(lds + addr + 32);
+      f.h[jj][st] = make_uint4(u0.x, u0.y, u1.x, u1.y);
+    }
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int addr = b8 + 256 * jj;
+    const uint2 u0 = *(const uint2*)(lds + addr);
+    const uint2 u1 = *(const uint2*)(lds + addr + 64);
+    const uint2 u2 = *(const uint2*)(lds + addr + 128);
+    const uint2 u3 = *(const uint2*)(lds + addr + 192);
+    f.e[jj][0] = make_uint4(u0.x, u0.y, u1.x, u1.y);
+    f.e[jj][1] = make_uint4(u2.x, u2.y, u3.x, u3.y);
+  }
+}
+
+// The MFMAs of one chunk on the pair P: the fp16 steps, then the residual step scaled by
+// 2^(sa - 127) * 2^(sb - 127).  Four MFMAs separate any two that share an accumulator.
+template <int MB, int NB, int P>
+__device__ __forceinline__ void f16f8_mma_pair(f32x16 (&acc)[MB][NB], const uint4 (&ha)[MB][2],
+                                               const uint4 (&ea)[MB][2], const F16F8Pair& f,
+                                               const int (&sa)[MB], int sb) {
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int t = 0; t < MB; ++t) {
+      const f16x8 av = __builtin_bit_cast(f16x8, ha[t][st]);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        acc[t][2 * P + jj] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+            av, __builtin_bit_cast(f16x8, f.h[jj][st]), acc[t][2 * P + jj], 0, 0, 0);
+    }
+#pragma unroll
+  for (int t = 0; t < MB; ++t) {
+    const i32x8 av = __builtin_bit_cast(i32x8, (U8{ea[t][0], ea[t][1]}));
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const i32x8 bv = __builtin_bit_cast(i32x8, (U8{f.e[jj][0], f.e[jj][1]}));
+      acc[t][2 * P + jj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+          av, bv, acc[t][2 * P + jj], 0, 0, 0, sa[t], 0, sb);
+    }
+  }
+}
+
+// One chunk c of the K-loop: NB / 2 pair steps.  Step P issues its MFMAs on slot P & 1 while
+// the next pair's strip fragments (chunk c's pair P + 1, or pair 0 of chunk cn) load into the
+// other slot; steps 0 and 1 also load the next chunk's template fragments (chunk cn, into
+// hn / en).  Strip reads have one step and template reads at least NB / 2 - 1 steps to
+// arrive in.
+template <int MB, int NB, int P>
+__device__ __forceinline__ void f16f8_steps(f32x16 (&acc)[MB][NB], const uint4 (&ha)[MB][2],
+                                            const uint4 (&ea)[MB][2], uint4 (&hn)[MB][2],
+                                            uint4 (&en)[MB][2], F16F8Pair (&slot)[2],
+                                            const char* lds, const void* bank, int64_t blk0,
+                                            int c, int cn, int nc, int off_w, int n, int h,
+                                            int lane, int plane_bytes, const int (&sa)[MB],
+                                            int sb) {
+  if constexpr (P < NB / 2) {
+    constexpr int NP = NB / 2;
+    constexpr int NVM = P < 2 ? 2 * MB : 0;     // template loads of this step
+    static_assert(NP >= 2, "two steps carry the template loads");
+    if constexpr (P + 1 < NP)
+      f16f8_load_pair(slot[(P + 1) & 1], lds, off_w, c, P + 1, n, h, plane_bytes);
+    else
+      f16f8_load_pair(slot[(P + 1) & 1], lds, off_w, cn, 0, n, h, plane_bytes);
+    const uint4* A = (const uint4*)bank;
+#pragma unroll
+    for (int i = 0; i < NVM; ++i) {
+      const int q = P * 2 * MB + i;             // 0 .. 4 MB - 1
+      const int t = (q >> 1) % MB, half = q & 1;
+      const bool is_e = q >= 2 * MB;
+      const int64_t idx = (((blk0 + t) * nc + cn) * 4 + (is_e ? 2 : 0) + half) * 64 + lane;
+      if (is_e) en[t][half] = A[idx]; else hn[t][half] = A[idx];
+    }
+    f16f8_mma_pair<MB, NB, P>(acc, ha, ea, slot[P & 1], sa, sb);
+    constexpr int NMF = 6 * MB;                 // MFMAs per step
+    _Pragma("unroll") for (int i_ = 0; i_ < NVM; ++i_) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    _Pragma("unroll") for (int i_ = 0; i_ < 8; ++i_) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    if constexpr (NMF > NVM + 8) __builtin_amdgcn_sched_group_barrier(0x008, NMF - NVM - 8, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    f16f8_steps<MB, NB, P + 1>(acc, ha, ea, hn, en, slot, lds, bank, blk0, c, cn, nc, off_w, n,
+                               h, lane, plane_bytes, sa, sb);
+  }
+}
+
 // Spectrogram / spectrum flush of the current bin for this wave's NB x 32 offsets.
 template <int NB>
 __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
@@ -634,8 +789,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 
   // ---- strip fill ----
   const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
-  int sb = 127;          // FP8: E8M0 scale undoing the strip's 2^e_x
-  float dscale = 1.0f;   // F16X2: 2^-(10 + e_x), undoing the template and strip scales
+  int sb = 127;          // FP8, F16F8: E8M0 scale of the strip's e4m3 codes
+  float dscale = 1.0f;   // F16X2, F16F8: 2^-(10 + e_x), undoing the template and strip scales
   if constexpr (PREC == P_FP32) {
     float* sx = (float*)lds;
     for (int i = tid; i < S; i += WG_THREADS) {
@@ -643,7 +798,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       float v = gi < sg.n ? sg.x[gi] : 0.0f;
       sx[i] = isfinite(v) ? v : 0.0f;
     }
-  } else if constexpr (PREC == P_FP8 || PREC == P_F16X2) {
+  } else if constexpr (PREC == P_FP8 || PREC == P_F16X2 || PREC == P_F16F8) {
     // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= LIM
     // (448 for e4m3, 2^14 for fp16)
     constexpr float LIM = PREC == P_FP8 ? 448.0f : 16384.0f;
@@ -679,6 +834,60 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
         w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], w1, true);
         *(uint2*)(lds + t * 8) = make_uint2((unsigned)w0, (unsigned)w1);
+      }
+    } else if constexpr (PREC == P_F16F8) {
+      dscale = ldexpf(1.0f, -(F16_TEMPLATE_EXP + ex));
+      sb = 127 + F8_XHI_SHIFT;
+      // cell t of the fp16 plane: fp16 of y = x[tau0 + t + e] * 2^e_x, e = 0..3; cell t of the
+      // two e4m3 planes: codes of fp16(y) * 2^-6 and of (y - fp16(y)) * 2^5, e = 0..7.
+      // |y| <= 2^14 and |y - fp16(y)| <= 4 keep both codes within 448.
+      const int plane_bytes = S * 8;
+      for (int t = tid; t < S; t += WG_THREADS) {
+        float yh[8], yl[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t gi = tau0 + t + e;
+          const float u = gi < sg.n ? sg.x[gi] : 0.0f;
+          const float y = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+          yh[e] = (float)(_Float16)y;
+          yl[e] = y - yh[e];
+        }
+        _Float16 hv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hv[e] = (_Float16)yh[e];
+        *(uint2*)(lds + t * 8) = __builtin_bit_cast(uint2, hv);
+        int w[4];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          int u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e], -F8_XHI_SHIFT),
+                                                  ldexpf(yh[4 * e + 1], -F8_XHI_SHIFT), 0, false);
+          w[e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e + 2], -F8_XHI_SHIFT),
+                                                 ldexpf(yh[4 * e + 3], -F8_XHI_SHIFT), u, true);
+          u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e], F8_XLO_EXP),
+                                              ldexpf(yl[4 * e + 1], F8_XLO_EXP), 0, false);
+          w[2 + e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e + 2], F8_XLO_EXP),
+                                                     ldexpf(yl[4 * e + 3], F8_XLO_EXP), u, true);
+        }
+        *(uint2*)(lds + plane_bytes + t * 8) = make_uint2((unsigned)w[0], (unsigned)w[1]);
+        *(uint2*)(lds + 2 * plane_bytes + t * 8) = make_uint2((unsigned)w[2], (unsigned)w[3]);
+      }
+      // per-offset epilogue operands, kept in LDS rather than in registers across the K-loop:
+      // 1/sqrt(E) and the window mean in accumulator units
+      const int n_wg = 32 * NB * WG_WAVES;
+      double* inv_l = (double*)(lds + 3 * plane_bytes);
+      float* mu_l = (float*)(inv_l + n_wg);
+      for (int i = tid; i < n_wg; i += WG_THREADS) {
+        const int64_t tau = tau0 + i;
+        double iv = 0.0;
+        float m = 0.0f;
+        if (tau < sg.W) {
+          iv = sg.inv_norm[tau];
+          const double* a = sg.pre + tau * 4;
+          const double* z = sg.pre + (tau + b.L) * 4;
+          m = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L) / dscale;
+        }
+        inv_l[i] = iv;
+        mu_l[i] = m;
       }
     } else {
       dscale = ldexpf(1.0f, -(F16_TEMPLATE_EXP + ex));
@@ -723,12 +932,26 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int plane_bytes = S * 8;
 
   double inv[NB];
-  float mu[NB];   // FP8: window means, for the template-sum correction
+  float mu[NB];   // FP8, F16F8: window means, for the template-sum correction
+  // F16F8 reads both from LDS after each tile's K-loop (its K-loop needs the registers); the
+  // empty asm keeps the reads inside the tile loop.
+  auto load_stats = [&]() {
+    int base = off_w + n;
+    asm volatile("" : "+v"(base));
+    const double* inv_l = (const double*)(lds + 3 * plane_bytes);
+    const float* mu_l = (const float*)(inv_l + 32 * NB * WG_WAVES);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      inv[j] = inv_l[base + 32 * j];
+      mu[j] = mu_l[base + 32 * j];
+    }
+  };
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int64_t tau = tau_w0 + 32 * j + n;
-    inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
+    inv[j] = 0.0;
     mu[j] = 0.0f;
+    if constexpr (PREC != P_F16F8) inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
     if constexpr (PREC == P_FP8) {
       if (tau < sg.W) {
         const double* a = sg.pre + tau * 4;
@@ -759,16 +982,36 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     int sa[MB];
 #pragma unroll
     for (int t = 0; t < MB; ++t)
-      sa[t] = PREC == P_FP8 ? 127 - b.texp[(blk0 + t) * 32 + n] : 127;
+      sa[t] = PREC == P_FP8     ? 127 - b.texp[(blk0 + t) * 32 + n]
+              : PREC == P_F16F8 ? 127 - b.texp[(blk0 + t) * 32 + n] -
+                                      (F8_LO_SHIFT - F16_TEMPLATE_EXP)
+                                : 127;
     // Software pipeline over chunk pairs (n_chunks is even): while the MFMAs of chunk c
     // run, the template fragments of chunk c+1 and the strip fragments of chunk c+1 are in
     // flight.  Scheduling barriers keep the compiler from sinking the loads next to their
     // uses.  The prefetches past the last chunk re-read a valid chunk and are unused.
     const int nc = b.n_chunks;
-    AFrag<PREC, MB> a0, a1;
     __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (PIPE == 1) {
+    if constexpr (PREC == P_F16F8) {
+      // Pair-streaming schedule (f16f8_steps): per chunk, NB / 2 steps over offset-block
+      // pairs; template fragments double-buffered across chunks, strip fragments across steps.
+      static_assert(F8_XLO_EXP == F8_LO_SHIFT - F8_XHI_SHIFT, "residual scales must agree");
+      static_assert(NB % 2 == 0 && 6 * MB >= 2 * MB + 8, "pair-step shape");
+      uint4 h0[MB][2], e0[MB][2], h1[MB][2], e1[MB][2];
+      F16F8Pair slot[2];
+      f16f8_load_a<MB>(h0, b.data, blk0, 0, nc, lane, 0);
+      f16f8_load_a<MB>(e0, b.data, blk0, 0, nc, lane, 2);
+      f16f8_load_pair(slot[0], lds, off_w, 0, 0, n, h, plane_bytes);
+      __builtin_amdgcn_sched_barrier(0);
+      for (int c = 0; c < nc; c += 2) {
+        const int c2 = c + 2 < nc ? c + 2 : nc - 1;
+        f16f8_steps<MB, NB, 0>(acc, h0, e0, h1, e1, slot, lds, b.data, blk0, c, c + 1, nc,
+                               off_w, n, h, lane, plane_bytes, sa, sb);
+        f16f8_steps<MB, NB, 0>(acc, h1, e1, h0, e0, slot, lds, b.data, blk0, c + 1, c2, nc,
+                               off_w, n, h, lane, plane_bytes, sa, sb);
+      }
+    } else if constexpr (PIPE == 1) {
       // Interleaved schedule.  The strip fragments live in two halves (offset blocks
       // [0, H) and [H, NB)); region (c, h) issues the MFMAs of half h of chunk c and, between
       // them, the LDS reads of the other half for the next region (half 1 of chunk c, or half
@@ -776,6 +1019,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       // loads never write registers its own MFMAs read.
       constexpr int H = NB / 2;
       BFrag<PREC, NB> bb;
+      AFrag<PREC, MB> a0, a1;
       load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
       load_b<PREC, NB, 0, H>(bb, lds, off_w, 0, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
@@ -819,6 +1063,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     } else if constexpr (NB <= 4) {
       // Two strip-fragment buffers: chunk c+1's fragments load while chunk c's MFMAs run.
       BFrag<PREC, NB> b0, b1;
+      AFrag<PREC, MB> a0, a1;
       load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
       load_b<PREC, NB>(b0, lds, off_w, 0, n, h, plane_bytes);
@@ -844,6 +1089,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       // half's MFMAs run.
       constexpr int H = NB / 2;
       BFrag<PREC, NB> bb;
+      AFrag<PREC, MB> a0, a1;
       load_a<PREC, MB>(a0, b.data, blk0, 0, nc, lane);
       __builtin_amdgcn_sched_barrier(0);
       load_b<PREC, NB, 0, NB>(bb, lds, off_w, 0, n, h, plane_bytes);
@@ -873,7 +1119,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       }
     }
 
-    if constexpr (PREC == P_FP8) {
+    if constexpr (PREC == P_F16F8) load_stats();
+    if constexpr (PREC == P_FP8 || PREC == P_F16F8) {
       // The rounded templates carry a small sum s_k, which would pick up s_k times the
       // window mean; d - mu * s_k is the contraction of the rounded template with the
       // centred window.
@@ -1082,7 +1329,8 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
 
 // The compiled kernel variants: (template blocks, offset blocks per wave, K-loop schedule)
 // for the search; the two passes of the tail search exist for each precision's default
-// shape only (2 x 8 interleaved for the split forms, 2 x 4 otherwise).
+// shape only (2 x 8 interleaved for the split forms, 2 x 8 split-phase for F16F8, 2 x 4
+// otherwise).
 #define BFLY_DISPATCH(FN, ...)                                                         \
   do {                                                                                 \
     const int v_ = p.pipe * 256 + p.tm * 16 + p.tn;                                    \
@@ -1100,6 +1348,9 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
       if (b.precision == P_FP8 && v_ == 0x024)                                         \
         return m1_ ? FN<P_FP8, 2, 4, 0, MODE_SIGMA>(__VA_ARGS__)                       \
                    : FN<P_FP8, 2, 4, 0, MODE_TAILS>(__VA_ARGS__);                      \
+      if (b.precision == P_F16F8 && v_ == 0x228)                                       \
+        return m1_ ? FN<P_F16F8, 2, 8, 2, MODE_SIGMA>(__VA_ARGS__)                     \
+                   : FN<P_F16F8, 2, 8, 2, MODE_TAILS>(__VA_ARGS__);                    \
       return hipErrorInvalidValue;                                                     \
     }                                                                                  \
     if (b.precision == P_FP32) {                                                       \
@@ -1119,12 +1370,15 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
       if (v_ == 0x024) return FN<P_FP8, 2, 4, 0, MODE_SEARCH>(__VA_ARGS__);            \
       if (v_ == 0x018) return FN<P_FP8, 1, 8, 0, MODE_SEARCH>(__VA_ARGS__);            \
       if (v_ == 0x128) return FN<P_FP8, 2, 8, 1, MODE_SEARCH>(__VA_ARGS__);            \
+    } else if (b.precision == P_F16F8) {                                               \
+      if (v_ == 0x228) return FN<P_F16F8, 2, 8, 2, MODE_SEARCH>(__VA_ARGS__);          \
     }                                                                                  \
     return hipErrorInvalidValue;                                                       \
   } while (0)
 
 bool main_variant_exists(int precision, int tm, int tn, int pipe, int mode) {
   const int v = pipe * 256 + tm * 16 + tn;
+  if (precision == P_F16F8) return v == 0x228;
   if (mode != MODE_SEARCH)
     return v == ((precision == P_BF16X3 || precision == P_F16X2) ? 0x128 : 0x024);
   if (precision == P_BF16X3)

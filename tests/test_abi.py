@@ -59,6 +59,15 @@ def test_bank_bytes_and_validation_on_host(lib):
     df.L = 4097
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(df)
+    # F16F8: four bytes per tap (fp16 + two e4m3 codes), the FP8 side tables; L_pad = 2048
+    # (multiple of 64) for L = 2000; L is capped by the strip's LDS footprint
+    dm = lib.make_desc(bank_params(3), "f16f8")
+    assert lib.bank_bytes(dm) == 720000 * 2048 * 4 + 720000 * 8 + 256
+    dm.L = 5249
+    with pytest.raises(lib.BflyError):
+        lib.bank_bytes(dm)
+    dm.L = 5248
+    assert lib.bank_bytes(dm) == 720000 * 5248 * 4 + 720000 * 8 + 256
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
         q = lib.make_desc(bank_params(2), "fp32")
