@@ -30,11 +30,12 @@ if ROOT not in sys.path:
 
 METRIC = "template×offset correlations/s vs plain FP32 at stated error; p50/p99 latency"
 # MI355X dense MFMA peaks; F16F8 is priced at the fp16 peak of its main product
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "f16x2": 2500.0, "f16f8": 2500.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "f16x2": 2500.0, "f16f8": 2500.0,
+               "f16f6": 2500.0}
 # MFMA products per tap, in units of one product at the priced peak (F16F8: one fp16
-# product plus two e4m3 products at twice the rate)
-MFMA_TERMS = {"fp32": 1, "bf16x3": 3, "f16x2": 2, "f16f8": 2}
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fft": 1e-5, "f16f8": 1e-4}
+# product plus two e4m3 products at twice the rate; F16F6: two e2m3 products at four times)
+MFMA_TERMS = {"fp32": 1, "bf16x3": 3, "f16x2": 2, "f16f8": 2, "f16f6": 1.5}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fft": 1e-5, "f16f8": 1e-4, "f16f6": 1e-4}
 
 
 def log(*a):
@@ -246,7 +247,7 @@ def kernel_tile(prec):
         return env
     if prec == "fft":
         return "fft"
-    if prec == "f16f8":
+    if prec in ("f16f8", "f16f6"):
         return "2x8p"
     return "2x8i" if prec in ("bf16x3", "f16x2") else "2x4"
 
@@ -290,7 +291,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32", "fft", "f16f8"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32", "fft", "f16f8", "f16f6"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--tails-kappa", type=float, default=5.0,
@@ -392,7 +393,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16", "f16x2": "f16", "f16f8": "f16+fp8"}.get(args.precision, "f32"),
+        "dtype": {"bf16x3": "bf16", "f16x2": "f16", "f16f8": "f16+fp8",
+                  "f16f6": "f16+fp6"}.get(args.precision, "f32"),
         "data": "synthetic",
         "config": {"workload": "strain-like 32 s at 4096 Hz (131,072 samples, SNR-8 chirp) + "
                                "time-randomised control; bank 256 f0 x 256 fdot = 65,536 "

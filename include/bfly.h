@@ -72,12 +72,15 @@ typedef enum {
   BF_FFT = 4,    /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
                     real FFTs of length N = 2M, M in 512..4096 minimising M log2 M per valid
                     output (N - L + 1); L <= 4096; the same outputs as the direct forms */
-  BF_F16F8 = 5   /* fp16 product of the fp16-rounded template and data, plus the two residual
+  BF_F16F8 = 5,  /* fp16 product of the fp16-rounded template and data, plus the two residual
                     products (template residual x data, template x data residual) as e4m3 codes
                     with power-of-two scales (per template, per strip) undone by the MFMA scale
                     operands; the rounded templates' sums times the window mean are
                     subtracted.  Two thirds of BF_BF16X3's MFMA time per tap; ~1e-5 to 3e-5
                     relative error, stated bound 1e-4; L <= 5248 */
+  BF_F16F6 = 6   /* as BF_F16F8 with the residual products in e2m3 (fp6) codes, whose MFMA
+                    runs at twice the e4m3 rate: half of BF_BF16X3's MFMA time per tap.
+                    Stated bound 1e-4; L <= 5248 */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;

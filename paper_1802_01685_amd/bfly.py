@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbfly.so")
 
 BF_OK, BF_EINVAL, BF_ENOMEM, BF_EBUDGET, BF_EAGAIN, BF_ENOTFOUND, BF_EHIP, BF_ECANCELED = (
     0, -1, -2, -3, -4, -5, -6, -7)
-PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp8": 2, "f16x2": 3, "fft": 4, "f16f8": 5}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp8": 2, "f16x2": 3, "fft": 4, "f16f8": 5, "f16f6": 6}
 NORMS = {"centred": 0, "raw": 1}
 STATUS_NAMES = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ENOMEM", -3: "BF_EBUDGET",
                 -4: "BF_EAGAIN", -5: "BF_ENOTFOUND", -6: "BF_EHIP", -7: "BF_ECANCELED"}

@@ -67,12 +67,13 @@ bf_status check_desc(const bf_bank_desc* d) {
       d->shard_count > d->n_f0)
     return fail(BF_EINVAL, "need 0 <= shard_index < shard_count <= n_f0");
   if (d->precision != BF_FP32 && d->precision != BF_BF16X3 && d->precision != BF_FP8 &&
-      d->precision != BF_F16X2 && d->precision != BF_FFT && d->precision != BF_F16F8)
+      d->precision != BF_F16X2 && d->precision != BF_FFT && d->precision != BF_F16F8 &&
+      d->precision != BF_F16F6)
     return fail(BF_EINVAL, "precision %d is not available", d->precision);
   if (d->precision == BF_FFT && d->L > MAX_FFT_L)
     return fail(BF_EINVAL, "the FFT form needs L <= %d", MAX_FFT_L);
-  if (d->precision == BF_F16F8 && d->L > MAX_F16F8_L)
-    return fail(BF_EINVAL, "the F16F8 form needs L <= %d", MAX_F16F8_L);
+  if ((d->precision == BF_F16F8 || d->precision == BF_F16F6) && d->L > MAX_F16F8_L)
+    return fail(BF_EINVAL, "the F16F8 and F16F6 forms need L <= %d", MAX_F16F8_L);
   const double v[4] = {d->f0_min, d->f0_max, d->fdot_min, d->fdot_max};
   for (double x : v)
     if (!std::isfinite(x)) return fail(BF_EINVAL, "grid bounds must be finite");
@@ -209,16 +210,17 @@ int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per C
 
 // Tile shape of the contraction kernel: tm template blocks x tn offset blocks (of 32) per
 // wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i|p] (e.g. "2x8i"; i = interleaved,
-// p = split-phase) overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
+// p = pair streaming) overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
 // depend on it (FP8 does, through its per-strip scales).
 void choose_tile(int precision, int mode, int32_t* tm, int32_t* tn, int32_t* pipe) {
   // Defaults from measurement on MI355X: the split forms are fastest with 2 x 8 blocks and
   // the interleaved schedule; FP32 (64-cycle MFMAs) and FP8 with 2 x 4.
-  // F16F8 has one shape, 2 x 8 with its split-phase schedule.
+  // F16F8 and F16F6 have one shape, 2 x 8 with their pair-streaming schedule.
   const bool split = precision == BF_BF16X3 || precision == BF_F16X2;
+  const bool f16r = precision == BF_F16F8 || precision == BF_F16F6;
   *tm = 2;
-  *tn = split || precision == BF_F16F8 ? 8 : 4;
-  *pipe = split ? 1 : precision == BF_F16F8 ? 2 : 0;
+  *tn = split || f16r ? 8 : 4;
+  *pipe = split ? 1 : f16r ? 2 : 0;
   const char* e = getenv("BF_TILE");
   int a = 0, c = 0;
   char il = 0;

@@ -22,12 +22,15 @@ constexpr int KCH_F16F8 = 32;                 // taps per chunk, F16F8 form
 constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG + L_pad
 constexpr int MAX_L = 8192;
 constexpr int MAX_FFT_L = 4096;              // FFT form: N = 2M <= 8192
-constexpr int MAX_F16F8_L = 5248;            // F16F8: 24-byte strip cells + 12 KB fill 160 KB LDS
+constexpr int MAX_F16F8_L = 5248;            // F16F8, F16F6: 24-byte strip cells + 12 KB
+                                             // fill 160 KB LDS
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
 constexpr double SIGMA_FIX_SCALE = 68719476736.0;   // 2^36: fixed-point sums of rho^2
 
-enum Precision { P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4, P_F16F8 = 5 };
+enum Precision {
+  P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4, P_F16F8 = 5, P_F16F6 = 6
+};
 
 // F16X2 and F16F8: templates are stored as fp16 (hi + lo) of h * 2^F16_TEMPLATE_EXP.
 constexpr int F16_TEMPLATE_EXP = 10;
@@ -39,13 +42,23 @@ constexpr int F8_LO_SHIFT = 11;
 constexpr int F8_XLO_EXP = 5;
 constexpr int F8_XHI_SHIFT = 6;
 
+// F16F6: as F16F8 with e2m3 residual codes (max 7.5).  Template codes: the residual scaled by
+// 2^(e_k + 11), the template by 2^e_k (e_k keeps max |h| * 2^e_k <= 7.5); strip codes: the
+// fp16 samples scaled by 2^-11 (the strip scale keeps them <= 15360 = 7.5 * 2^11) and the data
+// residual unscaled (|y - fp16(y)| <= 4).  Each lane half has its own MFMA scale pair.
+constexpr int F6_LO_SHIFT = 11;
+constexpr int F6_XHI_SHIFT = 11;
+constexpr float F6_STRIP_LIM = 15360.0f;
+
 // Taps per K-loop chunk; L_pad is a multiple of twice this.
 constexpr int chunk_taps(int precision) {
-  return precision == P_FP8 ? KCH_FP8 : precision == P_F16F8 ? KCH_F16F8 : KCH;
+  return precision == P_FP8 ? KCH_FP8 : (precision == P_F16F8 || precision == P_F16F6) ? KCH_F16F8 : KCH;
 }
+// The fp16 + low-precision residual forms (F16F8, F16F6).
+constexpr bool is_f16r(int precision) { return precision == P_F16F8 || precision == P_F16F6; }
 // Forms whose bank carries per-template exponents and template sums.
 constexpr bool has_side_tables(int precision) {
-  return precision == P_FP8 || precision == P_F16F8;
+  return precision == P_FP8 || is_f16r(precision);
 }
 
 // Per-series table entry, resident in the workspace (device).
@@ -142,6 +155,7 @@ enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2 };
 // allocation (templates, side tables, then a 256-byte status word).
 inline size_t bank_data_bytes(const BankDev& b) {
   if (b.precision == P_FFT) return (size_t)b.K_pad * (size_t)(b.fft_m + 2) * 8;  // spectra
+  if (b.precision == P_F16F6) return (size_t)b.K_pad * (size_t)b.L_pad / 2 * 7;  // 3.5 B/tap
   return (size_t)b.K_pad * (size_t)b.L_pad * (b.precision == P_FP8 ? 1 : 4);
 }
 // FP8 and F16F8 side tables after the codes: int32 exponent e_k [K_pad], then the float sum

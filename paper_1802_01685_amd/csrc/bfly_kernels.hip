@@ -65,6 +65,27 @@ __device__ __forceinline__ dd two_prod(double a, double b) {
   return {p, fma(a, b, -p)};
 }
 
+// OCP e2m3 (fp6): sign, 2 exponent bits (bias 1), 3 mantissa bits; max 7.5, subnormal step
+// 1/8.  Round to nearest even of |v| <= 7.5: below 1 the code is rint(8 |v|) (8 is the first
+// normal, 1.0); from 1 on, exponent e = floor(log2 |v|) and mantissa rint(8 (|v| 2^-e - 1)),
+// a mantissa of 8 carrying into the exponent field.  Every step but rint is exact.
+__device__ __forceinline__ uint32_t enc_e2m3(float v) {
+  const float a = fabsf(v);
+  uint32_t code;
+  if (a < 1.0f) {
+    code = (uint32_t)rintf(a * 8.0f);
+  } else {
+    const int e = (int)((__float_as_uint(a) >> 23) & 0xFF) - 127;   // 0, 1 or 2
+    code = (uint32_t)((e + 1) << 3) + (uint32_t)rintf((ldexpf(a, -e) - 1.0f) * 8.0f);
+  }
+  return code | (v < 0.0f ? 0x20u : 0u);
+}
+__device__ __forceinline__ double dec_e2m3(uint32_t c) {
+  const int e = (int)((c >> 3) & 3), m = (int)(c & 7);
+  const double a = e == 0 ? m / 8.0 : (1.0 + m / 8.0) * ldexp(1.0, e - 1);
+  return (c & 0x20u) ? -a : a;
+}
+
 // One chirp sample: cos(2 pi frac(f0 t + fdot t^2 / 2)), t = n / fs.
 __device__ __forceinline__ double chirp_sample(double fs, double f0, double fdot, int n) {
   double t = (double)n / fs;
@@ -103,6 +124,11 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 //   lane 32 + m those of h scaled by 2^e_k (codes i < 16 in plane 2, the rest in plane 3).
 //   texp[k] = e_k as for FP8; tsum[k] is the sum of fp16(h * 2^10) * 2^-10 plus the rounded
 //   residual, the template that multiplies the data's fp16 part.
+// F16F6 layout, per (b, 32-tap chunk c): as F16F8 with 3584 bytes: the fp16 planes 0 and 1,
+//   then each lane's 32 e2m3 codes packed 6 bits apart (code i at bit 6i of 192 bits), bits
+//   0..127 in plane 2 (64 x 16 bytes) and bits 128..191 in plane 3 (64 x 8 bytes).  Lane m
+//   carries the residual scaled by 2^(e_k + 11), lane 32 + m the template scaled by 2^e_k,
+//   with max |h| * 2^e_k <= 7.5.
 // Padding templates (k >= K) and padding taps (n >= L) are zero.  The word after the bank
 // counts templates whose centred norm vanished (they cannot be normalised).
 // ---------------------------------------------------------------------------------------
@@ -149,10 +175,40 @@ __global__ __launch_bounds__(256) void k_bank_gen(GridDev g, BankDev b, void* ds
         mx = fmax(mx, fabs((chirp_sample(g.fs, f0, fdot, n) - mu) / nrm));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    e8 = mx > 0.0 ? (int)floor(log2(448.0 / mx)) : 0;
+    const double lim = b.precision == P_F16F6 ? 7.5 : 448.0;   // largest code value
+    e8 = mx > 0.0 ? (int)floor(log2(lim / mx)) : 0;
     if (lane == 0) texp[k] = e8;
   }
-  for (int n = lane; n < b.L_pad; n += 64) {
+  if (b.precision == P_F16F6) {
+    // one 32-tap chunk per lane at a time: the lane packs its two 192-bit code strings
+    for (int c = lane; c < b.n_chunks; c += 64) {
+      uint32_t wl[6] = {0u, 0u, 0u, 0u, 0u, 0u}, wh[6] = {0u, 0u, 0u, 0u, 0u, 0u};
+      char* cbase = (char*)dst + ((int64_t)blk * b.n_chunks + c) * 3584;
+      for (int r = 0; r < 32; ++r) {
+        const int n = 32 * c + r;
+        const double h = (real && n < b.L) ? (chirp_sample(g.fs, f0, fdot, n) - mu) / nrm : 0.0;
+        const _Float16 t16 = (_Float16)ldexp(h, F16_TEMPLATE_EXP);
+        const double rr = h - ldexp((double)t16, -F16_TEMPLATE_EXP);
+        const uint32_t cl = enc_e2m3((float)ldexp(rr, e8 + F6_LO_SHIFT));
+        const uint32_t ch = enc_e2m3((float)ldexp(h, e8));
+        qsum += ldexp((double)t16, e8 - F16_TEMPLATE_EXP) + ldexp(dec_e2m3(cl), -F6_LO_SHIFT);
+        const int q = r >> 4, hh = (r >> 3) & 1, i = r & 7;
+        *(_Float16*)(cbase + q * 1024 + (hh * 32 + m) * 16 + i * 2) = t16;
+        const int bit = 6 * r, w = bit >> 5, o = bit & 31;
+        wl[w] |= cl << o;
+        wh[w] |= ch << o;
+        if (o > 26) {
+          wl[w + 1] |= cl >> (32 - o);
+          wh[w + 1] |= ch >> (32 - o);
+        }
+      }
+      *(uint4*)(cbase + 2048 + m * 16) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+      *(uint4*)(cbase + 2048 + (32 + m) * 16) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+      *(uint2*)(cbase + 3072 + m * 8) = make_uint2(wl[4], wl[5]);
+      *(uint2*)(cbase + 3072 + (32 + m) * 8) = make_uint2(wh[4], wh[5]);
+    }
+  }
+  for (int n = lane; n < b.L_pad && b.precision != P_F16F6; n += 64) {
     const double h = (real && n < b.L) ? (chirp_sample(g.fs, f0, fdot, n) - mu) / nrm : 0.0;
     if (b.precision == P_FP32) {
       const int c = n >> 4, r = n & 15;
@@ -405,9 +461,9 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 // ---------------------------------------------------------------------------------------
 size_t main_lds_bytes(int precision, int L_pad, int n_wg) {
   const size_t S = (size_t)n_wg + (size_t)L_pad + STRIP_SLACK;
-  // F16F8: fp16 plane + two e4m3 planes, then the item's 1/sqrt(E) (double) and window
+  // F16F8, F16F6: fp16 plane + two code planes, then the item's 1/sqrt(E) (double) and window
   // means (float)
-  if (precision == P_F16F8) return S * 24 + (size_t)n_wg * 12;
+  if (is_f16r(precision)) return S * 24 + (size_t)n_wg * 12;
   return precision == P_FP32 ? S * 4 : (precision == P_FP8 || precision == P_F16X2) ? S * 8 : S * 16;
 }
 
@@ -601,17 +657,28 @@ __device__ __forceinline__ void mma_chunk(f32x16 (&acc)[MB][NB], const AFrag<PRE
   }
 }
 
-// F16F8 fragments.  Template planes q0, q0 + 1 of chunk c (q0 = 0: the fp16 steps, q0 = 2:
-// the e4m3 step).
-template <int MB>
+// F16F8 / F16F6 template fragments of chunk c: the fp16 planes (code = false) or the residual
+// step's code planes (code = true; F16F6 keeps bits 128..191 in the low half of v[t][1]).
+template <int PREC>
+__device__ __forceinline__ uint4 f16r_load_plane(const void* bank, int64_t blk, int c,
+                                                 int nchunks, int lane, int q) {
+  if constexpr (PREC == P_F16F8) {
+    return ((const uint4*)bank)[((blk * nchunks + c) * 4 + q) * 64 + lane];
+  } else {
+    const char* base = (const char*)bank + (blk * nchunks + c) * 3584;
+    if (q < 3) return *(const uint4*)(base + q * 1024 + lane * 16);
+    const uint2 u = *(const uint2*)(base + 3072 + lane * 8);
+    return make_uint4(u.x, u.y, 0u, 0u);
+  }
+}
+
+template <int PREC, int MB>
 __device__ __forceinline__ void f16f8_load_a(uint4 (&v)[MB][2], const void* bank, int64_t blk0,
                                              int c, int nchunks, int lane, int q0) {
-  const uint4* A = (const uint4*)bank;
 #pragma unroll
   for (int t = 0; t < MB; ++t) {
-    const int64_t idx = (((blk0 + t) * nchunks + c) * 4 + q0) * 64 + lane;
-    v[t][0] = A[idx];
-    v[t][1] = A[idx + 64];
+    v[t][0] = f16r_load_plane<PREC>(bank, blk0 + t, c, nchunks, lane, q0);
+    v[t][1] = f16r_load_plane<PREC>(bank, blk0 + t, c, nchunks, lane, q0 + 1);
   }
 }
 
@@ -649,9 +716,24 @@ __device__ __forceinline__ void f16f8_load_pair(F16F8Pair& f, const char* lds, i
   }
 }
 
-// The MFMAs of one chunk on the pair P: the fp16 steps, then the residual step scaled by
-// 2^(sa - 127) * 2^(sb - 127).  Four MFMAs separate any two that share an accumulator.
-template <int MB, int NB, int P>
+// e2m3 strip operand: the four 8-byte cells hold 48 code bits each; packed 6 bits apart.
+__device__ __forceinline__ i32x8 f6_pack(const uint4& c01, const uint4& c23) {
+  i32x8 v;
+  v[0] = (int)c01.x;
+  v[1] = (int)(c01.y | (c01.z << 16));
+  v[2] = (int)((c01.z >> 16) | (c01.w << 16));
+  v[3] = (int)c23.x;
+  v[4] = (int)(c23.y | (c23.z << 16));
+  v[5] = (int)((c23.z >> 16) | (c23.w << 16));
+  v[6] = 0;
+  v[7] = 0;
+  return v;
+}
+
+// The MFMAs of one chunk on the pair P: the fp16 steps, then the residual step (e4m3 or
+// e2m3 codes) scaled by 2^(sa - 127) * 2^(sb - 127).  Four MFMAs separate any two that share
+// an accumulator.
+template <int PREC, int MB, int NB, int P>
 __device__ __forceinline__ void f16f8_mma_pair(f32x16 (&acc)[MB][NB], const uint4 (&ha)[MB][2],
                                                const uint4 (&ea)[MB][2], const F16F8Pair& f,
                                                const int (&sa)[MB], int sb) {
@@ -665,15 +747,19 @@ __device__ __forceinline__ void f16f8_mma_pair(f32x16 (&acc)[MB][NB], const uint
         acc[t][2 * P + jj] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
             av, __builtin_bit_cast(f16x8, f.h[jj][st]), acc[t][2 * P + jj], 0, 0, 0);
     }
+  constexpr int FMT = PREC == P_F16F8 ? 0 : 2;   // e4m3 : e2m3
+  i32x8 bv[2];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+    bv[jj] = PREC == P_F16F8 ? __builtin_bit_cast(i32x8, (U8{f.e[jj][0], f.e[jj][1]}))
+                             : f6_pack(f.e[jj][0], f.e[jj][1]);
 #pragma unroll
   for (int t = 0; t < MB; ++t) {
     const i32x8 av = __builtin_bit_cast(i32x8, (U8{ea[t][0], ea[t][1]}));
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const i32x8 bv = __builtin_bit_cast(i32x8, (U8{f.e[jj][0], f.e[jj][1]}));
+    for (int jj = 0; jj < 2; ++jj)
       acc[t][2 * P + jj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-          av, bv, acc[t][2 * P + jj], 0, 0, 0, sa[t], 0, sb);
-    }
+          av, bv[jj], acc[t][2 * P + jj], FMT, FMT, 0, sa[t], 0, sb);
   }
 }
 
@@ -682,7 +768,7 @@ __device__ __forceinline__ void f16f8_mma_pair(f32x16 (&acc)[MB][NB], const uint
 // other slot; steps 0 and 1 also load the next chunk's template fragments (chunk cn, into
 // hn / en).  Strip reads have one step and template reads at least NB / 2 - 1 steps to
 // arrive in.
-template <int MB, int NB, int P>
+template <int PREC, int MB, int NB, int P>
 __device__ __forceinline__ void f16f8_steps(f32x16 (&acc)[MB][NB], const uint4 (&ha)[MB][2],
                                             const uint4 (&ea)[MB][2], uint4 (&hn)[MB][2],
                                             uint4 (&en)[MB][2], F16F8Pair (&slot)[2],
@@ -698,16 +784,15 @@ __device__ __forceinline__ void f16f8_steps(f32x16 (&acc)[MB][NB], const uint4 (
       f16f8_load_pair(slot[(P + 1) & 1], lds, off_w, c, P + 1, n, h, plane_bytes);
     else
       f16f8_load_pair(slot[(P + 1) & 1], lds, off_w, cn, 0, n, h, plane_bytes);
-    const uint4* A = (const uint4*)bank;
 #pragma unroll
     for (int i = 0; i < NVM; ++i) {
       const int q = P * 2 * MB + i;             // 0 .. 4 MB - 1
       const int t = (q >> 1) % MB, half = q & 1;
       const bool is_e = q >= 2 * MB;
-      const int64_t idx = (((blk0 + t) * nc + cn) * 4 + (is_e ? 2 : 0) + half) * 64 + lane;
-      if (is_e) en[t][half] = A[idx]; else hn[t][half] = A[idx];
+      const uint4 v = f16r_load_plane<PREC>(bank, blk0 + t, cn, nc, lane, (is_e ? 2 : 0) + half);
+      if (is_e) en[t][half] = v; else hn[t][half] = v;
     }
-    f16f8_mma_pair<MB, NB, P>(acc, ha, ea, slot[P & 1], sa, sb);
+    f16f8_mma_pair<PREC, MB, NB, P>(acc, ha, ea, slot[P & 1], sa, sb);
     constexpr int NMF = 6 * MB;                 // MFMAs per step
     _Pragma("unroll") for (int i_ = 0; i_ < NVM; ++i_) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -719,8 +804,8 @@ __device__ __forceinline__ void f16f8_steps(f32x16 (&acc)[MB][NB], const uint4 (
     }
     if constexpr (NMF > NVM + 8) __builtin_amdgcn_sched_group_barrier(0x008, NMF - NVM - 8, 0);
     __builtin_amdgcn_sched_barrier(0);
-    f16f8_steps<MB, NB, P + 1>(acc, ha, ea, hn, en, slot, lds, bank, blk0, c, cn, nc, off_w, n,
-                               h, lane, plane_bytes, sa, sb);
+    f16f8_steps<PREC, MB, NB, P + 1>(acc, ha, ea, hn, en, slot, lds, bank, blk0, c, cn, nc,
+                                     off_w, n, h, lane, plane_bytes, sa, sb);
   }
 }
 
@@ -789,8 +874,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 
   // ---- strip fill ----
   const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
-  int sb = 127;          // FP8, F16F8: E8M0 scale of the strip's e4m3 codes
-  float dscale = 1.0f;   // F16X2, F16F8: 2^-(10 + e_x), undoing the template and strip scales
+  int sb = 127;          // FP8, F16F8, F16F6: E8M0 scale of the strip's codes (per lane)
+  float dscale = 1.0f;   // F16X2, F16F8, F16F6: 2^-(10 + e_x), undoing both power-of-two scales
   if constexpr (PREC == P_FP32) {
     float* sx = (float*)lds;
     for (int i = tid; i < S; i += WG_THREADS) {
@@ -798,10 +883,10 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       float v = gi < sg.n ? sg.x[gi] : 0.0f;
       sx[i] = isfinite(v) ? v : 0.0f;
     }
-  } else if constexpr (PREC == P_FP8 || PREC == P_F16X2 || PREC == P_F16F8) {
+  } else if constexpr (PREC == P_FP8 || PREC == P_F16X2 || is_f16r(PREC)) {
     // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= LIM
-    // (448 for e4m3, 2^14 for fp16)
-    constexpr float LIM = PREC == P_FP8 ? 448.0f : 16384.0f;
+    // (448 for e4m3, 2^14 for fp16, 7.5 * 2^11 when the fp16 samples become e2m3 codes)
+    constexpr float LIM = PREC == P_FP8 ? 448.0f : PREC == P_F16F6 ? F6_STRIP_LIM : 16384.0f;
     __shared__ float wmax[WG_WAVES];
     float mx = 0.0f;
     for (int i = tid; i < S; i += WG_THREADS) {
@@ -835,12 +920,16 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         w1 = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], w1, true);
         *(uint2*)(lds + t * 8) = make_uint2((unsigned)w0, (unsigned)w1);
       }
-    } else if constexpr (PREC == P_F16F8) {
+    } else if constexpr (is_f16r(PREC)) {
       dscale = ldexpf(1.0f, -(F16_TEMPLATE_EXP + ex));
-      sb = 127 + F8_XHI_SHIFT;
+      // F16F6: each lane half scales its own operands (h = 0 the fp16 samples, h = 1 the
+      // data residual); the F16F6 template scale adds 2^-10 on both halves.
+      sb = PREC == P_F16F8 ? 127 + F8_XHI_SHIFT
+                           : 127 + F16_TEMPLATE_EXP + (h == 0 ? F6_XHI_SHIFT : 0);
       // cell t of the fp16 plane: fp16 of y = x[tau0 + t + e] * 2^e_x, e = 0..3; cell t of the
-      // two e4m3 planes: codes of fp16(y) * 2^-6 and of (y - fp16(y)) * 2^5, e = 0..7.
-      // |y| <= 2^14 and |y - fp16(y)| <= 4 keep both codes within 448.
+      // two code planes: codes of fp16(y) * 2^-6 and of (y - fp16(y)) * 2^5 (e4m3), or of
+      // fp16(y) * 2^-11 and y - fp16(y) (e2m3, 48 bits in 8 bytes), e = 0..7.  |y| <= 2^14
+      // (F16F6: 15360) and |y - fp16(y)| <= 4 keep the codes within 448 (7.5).
       const int plane_bytes = S * 8;
       for (int t = tid; t < S; t += WG_THREADS) {
         float yh[8], yl[8];
@@ -857,16 +946,29 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         for (int e = 0; e < 4; ++e) hv[e] = (_Float16)yh[e];
         *(uint2*)(lds + t * 8) = __builtin_bit_cast(uint2, hv);
         int w[4];
+        if constexpr (PREC == P_F16F8) {
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          int u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e], -F8_XHI_SHIFT),
-                                                  ldexpf(yh[4 * e + 1], -F8_XHI_SHIFT), 0, false);
-          w[e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e + 2], -F8_XHI_SHIFT),
-                                                 ldexpf(yh[4 * e + 3], -F8_XHI_SHIFT), u, true);
-          u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e], F8_XLO_EXP),
-                                              ldexpf(yl[4 * e + 1], F8_XLO_EXP), 0, false);
-          w[2 + e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e + 2], F8_XLO_EXP),
-                                                     ldexpf(yl[4 * e + 3], F8_XLO_EXP), u, true);
+          for (int e = 0; e < 2; ++e) {
+            int u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e], -F8_XHI_SHIFT),
+                                                    ldexpf(yh[4 * e + 1], -F8_XHI_SHIFT), 0, false);
+            w[e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yh[4 * e + 2], -F8_XHI_SHIFT),
+                                                   ldexpf(yh[4 * e + 3], -F8_XHI_SHIFT), u, true);
+            u = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e], F8_XLO_EXP),
+                                                ldexpf(yl[4 * e + 1], F8_XLO_EXP), 0, false);
+            w[2 + e] = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(yl[4 * e + 2], F8_XLO_EXP),
+                                                       ldexpf(yl[4 * e + 3], F8_XLO_EXP), u, true);
+          }
+        } else {
+          uint64_t ph = 0, pl = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            ph |= (uint64_t)enc_e2m3(ldexpf(yh[e], -F6_XHI_SHIFT)) << (6 * e);
+            pl |= (uint64_t)enc_e2m3(yl[e]) << (6 * e);
+          }
+          w[0] = (int)(uint32_t)ph;
+          w[1] = (int)(uint32_t)(ph >> 32);
+          w[2] = (int)(uint32_t)pl;
+          w[3] = (int)(uint32_t)(pl >> 32);
         }
         *(uint2*)(lds + plane_bytes + t * 8) = make_uint2((unsigned)w[0], (unsigned)w[1]);
         *(uint2*)(lds + 2 * plane_bytes + t * 8) = make_uint2((unsigned)w[2], (unsigned)w[3]);
@@ -951,7 +1053,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     const int64_t tau = tau_w0 + 32 * j + n;
     inv[j] = 0.0;
     mu[j] = 0.0f;
-    if constexpr (PREC != P_F16F8) inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
+    if constexpr (!is_f16r(PREC)) inv[j] = tau < sg.W ? sg.inv_norm[tau] : 0.0;
     if constexpr (PREC == P_FP8) {
       if (tau < sg.W) {
         const double* a = sg.pre + tau * 4;
@@ -985,6 +1087,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       sa[t] = PREC == P_FP8     ? 127 - b.texp[(blk0 + t) * 32 + n]
               : PREC == P_F16F8 ? 127 - b.texp[(blk0 + t) * 32 + n] -
                                       (F8_LO_SHIFT - F16_TEMPLATE_EXP)
+              : PREC == P_F16F6 ? 127 - b.texp[(blk0 + t) * 32 + n] - (h == 0 ? F6_LO_SHIFT : 0)
                                 : 127;
     // Software pipeline over chunk pairs (n_chunks is even): while the MFMAs of chunk c
     // run, the template fragments of chunk c+1 and the strip fragments of chunk c+1 are in
@@ -993,23 +1096,23 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     const int nc = b.n_chunks;
     __builtin_amdgcn_s_waitcnt(0);   // drain the previous tile's atomics before the pipeline
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (PREC == P_F16F8) {
+    if constexpr (is_f16r(PREC)) {
       // Pair-streaming schedule (f16f8_steps): per chunk, NB / 2 steps over offset-block
       // pairs; template fragments double-buffered across chunks, strip fragments across steps.
       static_assert(F8_XLO_EXP == F8_LO_SHIFT - F8_XHI_SHIFT, "residual scales must agree");
       static_assert(NB % 2 == 0 && 6 * MB >= 2 * MB + 8, "pair-step shape");
       uint4 h0[MB][2], e0[MB][2], h1[MB][2], e1[MB][2];
       F16F8Pair slot[2];
-      f16f8_load_a<MB>(h0, b.data, blk0, 0, nc, lane, 0);
-      f16f8_load_a<MB>(e0, b.data, blk0, 0, nc, lane, 2);
+      f16f8_load_a<PREC, MB>(h0, b.data, blk0, 0, nc, lane, 0);
+      f16f8_load_a<PREC, MB>(e0, b.data, blk0, 0, nc, lane, 2);
       f16f8_load_pair(slot[0], lds, off_w, 0, 0, n, h, plane_bytes);
       __builtin_amdgcn_sched_barrier(0);
       for (int c = 0; c < nc; c += 2) {
         const int c2 = c + 2 < nc ? c + 2 : nc - 1;
-        f16f8_steps<MB, NB, 0>(acc, h0, e0, h1, e1, slot, lds, b.data, blk0, c, c + 1, nc,
-                               off_w, n, h, lane, plane_bytes, sa, sb);
-        f16f8_steps<MB, NB, 0>(acc, h1, e1, h0, e0, slot, lds, b.data, blk0, c + 1, c2, nc,
-                               off_w, n, h, lane, plane_bytes, sa, sb);
+        f16f8_steps<PREC, MB, NB, 0>(acc, h0, e0, h1, e1, slot, lds, b.data, blk0, c, c + 1,
+                                     nc, off_w, n, h, lane, plane_bytes, sa, sb);
+        f16f8_steps<PREC, MB, NB, 0>(acc, h1, e1, h0, e0, slot, lds, b.data, blk0, c + 1, c2,
+                                     nc, off_w, n, h, lane, plane_bytes, sa, sb);
       }
     } else if constexpr (PIPE == 1) {
       // Interleaved schedule.  The strip fragments live in two halves (offset blocks
@@ -1119,8 +1222,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       }
     }
 
-    if constexpr (PREC == P_F16F8) load_stats();
-    if constexpr (PREC == P_FP8 || PREC == P_F16F8) {
+    if constexpr (is_f16r(PREC)) load_stats();
+    if constexpr (PREC == P_FP8 || is_f16r(PREC)) {
       // The rounded templates carry a small sum s_k, which would pick up s_k times the
       // window mean; d - mu * s_k is the contraction of the rounded template with the
       // centred window.
@@ -1329,8 +1432,8 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
 
 // The compiled kernel variants: (template blocks, offset blocks per wave, K-loop schedule)
 // for the search; the two passes of the tail search exist for each precision's default
-// shape only (2 x 8 interleaved for the split forms, 2 x 8 split-phase for F16F8, 2 x 4
-// otherwise).
+// shape only (2 x 8 interleaved for the split forms, 2 x 8 pair streaming for F16F8 and
+// F16F6, 2 x 4 otherwise).
 #define BFLY_DISPATCH(FN, ...)                                                         \
   do {                                                                                 \
     const int v_ = p.pipe * 256 + p.tm * 16 + p.tn;                                    \
@@ -1351,6 +1454,9 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
       if (b.precision == P_F16F8 && v_ == 0x228)                                       \
         return m1_ ? FN<P_F16F8, 2, 8, 2, MODE_SIGMA>(__VA_ARGS__)                     \
                    : FN<P_F16F8, 2, 8, 2, MODE_TAILS>(__VA_ARGS__);                    \
+      if (b.precision == P_F16F6 && v_ == 0x228)                                       \
+        return m1_ ? FN<P_F16F6, 2, 8, 2, MODE_SIGMA>(__VA_ARGS__)                     \
+                   : FN<P_F16F6, 2, 8, 2, MODE_TAILS>(__VA_ARGS__);                    \
       return hipErrorInvalidValue;                                                     \
     }                                                                                  \
     if (b.precision == P_FP32) {                                                       \
@@ -1372,13 +1478,15 @@ static hipError_t launch_main_t(const BatchHdr* hdr, int64_t blocks, const BankD
       if (v_ == 0x128) return FN<P_FP8, 2, 8, 1, MODE_SEARCH>(__VA_ARGS__);            \
     } else if (b.precision == P_F16F8) {                                               \
       if (v_ == 0x228) return FN<P_F16F8, 2, 8, 2, MODE_SEARCH>(__VA_ARGS__);          \
+    } else if (b.precision == P_F16F6) {                                               \
+      if (v_ == 0x228) return FN<P_F16F6, 2, 8, 2, MODE_SEARCH>(__VA_ARGS__);          \
     }                                                                                  \
     return hipErrorInvalidValue;                                                       \
   } while (0)
 
 bool main_variant_exists(int precision, int tm, int tn, int pipe, int mode) {
   const int v = pipe * 256 + tm * 16 + tn;
-  if (precision == P_F16F8) return v == 0x228;
+  if (is_f16r(precision)) return v == 0x228;
   if (mode != MODE_SEARCH)
     return v == ((precision == P_BF16X3 || precision == P_F16X2) ? 0x128 : 0x024);
   if (precision == P_BF16X3)

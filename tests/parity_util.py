@@ -15,7 +15,8 @@ from oracle import bfly_oracle as O
 # about 0.05 / sqrt(L) in rho: about 1% of m at the median, and up to ~7% of m (~15% of a
 # small spectrogram entry, relative to the 1/sqrt(L) floor) on templates of 37-64 taps.
 # The FFT form computes in float32 (spectra, transforms, products): the FP32 bound.
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fp8": 0.2, "fft": 1e-5, "f16f8": 1e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "f16x2": 1e-3, "fp8": 0.2, "fft": 1e-5, "f16f8": 1e-4,
+       "f16f6": 1e-4}
 
 
 def to_np(out: dict) -> dict:

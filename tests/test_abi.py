@@ -68,6 +68,12 @@ def test_bank_bytes_and_validation_on_host(lib):
         lib.bank_bytes(dm)
     dm.L = 5248
     assert lib.bank_bytes(dm) == 720000 * 5248 * 4 + 720000 * 8 + 256
+    # F16F6: fp16 (2 bytes) + two 6-bit codes per tap = 3.5 bytes, the same side tables
+    d6 = lib.make_desc(bank_params(3), "f16f6")
+    assert lib.bank_bytes(d6) == 720000 * 2048 * 7 // 2 + 720000 * 8 + 256
+    d6.L = 5249
+    with pytest.raises(lib.BflyError):
+        lib.bank_bytes(d6)
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
         q = lib.make_desc(bank_params(2), "fp32")

@@ -23,7 +23,7 @@ from synth import (BankParams, bank_params, cfg1_series, cfg2_series, cfg3_serie
 from tests.parity_util import TOL, check_against_oracle, check_hist, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-PRECS = ["fp32", "bf16x3", "f16x2", "fp8", "fft", "f16f8"]
+PRECS = ["fp32", "bf16x3", "f16x2", "fp8", "fft", "f16f8", "f16f6"]
 
 
 @pytest.fixture(scope="module")

@@ -20,7 +20,7 @@ from synth import BankParams, bank_params, cfg1_series, time_randomised, white_n
 from tests.parity_util import TOL, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-PRECS = ["fp32", "bf16x3", "f16x2", "fp8", "fft", "f16f8"]
+PRECS = ["fp32", "bf16x3", "f16x2", "fp8", "fft", "f16f8", "f16f6"]
 
 SMALL = BankParams(fs=128.0, L=48, n_f0=5, n_fdot=7, f0_min=3.0, f0_max=40.0,
                    fdot_min=-30.0, fdot_max=25.0)
