@@ -233,7 +233,8 @@ def serving_leg(bf, prec, n_segments, budget_gib, slots):
     stats = bf.server_stats(srv)
     bf.server_destroy(srv)
     del bank
-    return {"workload": "serving: 512 x 512 bank (262,144 templates), L = 4096, 1-64 s "
+    return {"precision_form": prec,
+            "workload": "serving: 512 x 512 bank (262,144 templates), L = 4096, 1-64 s "
                         "two-channel segments, HBM budget %d GiB, %d slots, 2 ticks in flight"
                         % (budget_gib, slots),
             "literal_50_per_s": literal, "at_70pct_capacity": scaled,
@@ -291,16 +292,21 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f16x2", "fp32", "fft", "f16f8", "f16f6"])
+    ap.add_argument("--precision", default="f16f6",
+                    choices=["bf16x3", "f16x2", "fp32", "fft", "f16f8", "f16f6"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="steps of the FP32 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--tails-kappa", type=float, default=5.0,
                     help="search depth of the kappa-sigma tail leg (0 skips it)")
-    ap.add_argument("--extra-forms", default="f16x2,fft",
+    ap.add_argument("--extra-forms", default="bf16x3,f16f8,f16x2,fft",
                     help="comma-separated further precision forms to time and check ('' skips)")
-    ap.add_argument("--cpu-offsets", type=int, default=8192, help="0 skips the oracle leg")
+    ap.add_argument("--cpu-offsets", type=int, default=16384, help="0 skips the oracle leg")
     ap.add_argument("--serve-segments", type=int, default=16,
                     help="segments per point of the serving leg (0 skips it)")
+    ap.add_argument("--serve-precision", default="bf16x3",
+                    choices=["bf16x3", "f16x2", "fp32", "fft", "f16f8", "f16f6"],
+                    help="form of the serving leg's device-resident bank (the chosen form and "
+                         "the FFT form are served beside it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a known-size reference "
                          "for hardware byte counters)")
@@ -373,12 +379,15 @@ def main() -> int:
     serving_other = {}
     if args.serve_segments > 0:
         log(f"serving leg: {args.serve_segments} segments per point")
-        serving = serving_leg(bf, args.precision, args.serve_segments, 32, 16)
+        serving = serving_leg(bf, args.serve_precision, args.serve_segments, 32, 16)
         log(f"  {serving}")
-        if args.precision != "fft" and "fft" in args.extra_forms.split(","):
-            log("serving leg on the FFT form")
-            serving_other["fft"] = serving_leg(bf, "fft", args.serve_segments, 32, 16)
-            log(f"  {serving_other['fft']}")
+        for form in dict.fromkeys([args.precision, "fft"]):
+            if form == args.serve_precision or (form == "fft" and
+                                                "fft" not in args.extra_forms.split(",")):
+                continue
+            log(f"serving leg on the {form} form")
+            serving_other[form] = serving_leg(bf, form, args.serve_segments, 32, 16)
+            log(f"  {serving_other[form]}")
 
     steps_ms = main_res["step_ms"]
     lat = serving["at_70pct_capacity"] if serving else None

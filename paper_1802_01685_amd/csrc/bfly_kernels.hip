@@ -842,6 +842,11 @@ __device__ __forceinline__ void flush_bin(const SegDesc& sg, const BankDev& b,
   if (lane == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
 }
 
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 // One work item: strip fill, template sweep, flushes.  PIPE selects the K-loop schedule,
 // MODE the pass (MainMode).
 template <int PREC, int MB, int NB, int PIPE, int MODE>
@@ -1041,12 +1046,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     int base = off_w + n;
     asm volatile("" : "+v"(base));
     const double* inv_l = (const double*)(lds + 3 * plane_bytes);
-    const float* mu_l = (const float*)(inv_l + 32 * NB * WG_WAVES);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      inv[j] = inv_l[base + 32 * j];
-      mu[j] = mu_l[base + 32 * j];
-    }
+    for (int j = 0; j < NB; ++j) inv[j] = inv_l[base + 32 * j];
   };
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -1222,26 +1223,33 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       }
     }
 
-    if constexpr (is_f16r(PREC)) load_stats();
+    // The rounded templates of the FP8, F16F8 and F16F6 forms carry a small sum s_k, which
+    // would pick up s_k times the window mean; d - mu * s_k is the contraction of the rounded
+    // template with the centred window.  The correction is the rank-1 product of the template
+    // sums and the negated window means: one v_mfma_f32_32x32x2_f32 per accumulator block,
+    // with the sums and means in K slot 0 (lanes h = 0) and zeros in slot 1.
     if constexpr (PREC == P_FP8 || is_f16r(PREC)) {
-      // The rounded templates carry a small sum s_k, which would pick up s_k times the
-      // window mean; d - mu * s_k is the contraction of the rounded template with the
-      // centred window.
-      const float* ts = b.tsum + blk0 * 32 + 4 * h;
+      float as[MB], bm[NB];
+#pragma unroll
+      for (int t = 0; t < MB; ++t) as[t] = h == 0 ? b.tsum[(blk0 + t) * 32 + n] : 0.0f;
+      if constexpr (is_f16r(PREC)) {
+        int base = off_w + n;
+        asm volatile("" : "+v"(base));   // read inside the tile loop, not kept across it
+        const float* mu_l = (const float*)((const double*)(lds + 3 * plane_bytes) +
+                                           32 * NB * WG_WAVES);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bm[j] = h == 0 ? -mu_l[base + 32 * j] : 0.0f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bm[j] = h == 0 ? -mu[j] : 0.0f;
+      }
 #pragma unroll
       for (int t = 0; t < MB; ++t)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const float4 s4 = *(const float4*)(ts + t * 32 + 8 * g);
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            acc[t][j][4 * g + 0] = fmaf(-mu[j], s4.x, acc[t][j][4 * g + 0]);
-            acc[t][j][4 * g + 1] = fmaf(-mu[j], s4.y, acc[t][j][4 * g + 1]);
-            acc[t][j][4 * g + 2] = fmaf(-mu[j], s4.z, acc[t][j][4 * g + 2]);
-            acc[t][j][4 * g + 3] = fmaf(-mu[j], s4.w, acc[t][j][4 * g + 3]);
-          }
-        }
+        for (int j = 0; j < NB; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[t], bm[j], acc[t][j], 0, 0, 0);
     }
+    if constexpr (is_f16r(PREC)) load_stats();
 
     // ---- epilogue: lane rows are 32t + 8g + 4h + i4 of the tile ----
     const int64_t kbase = kt * (32 * MB);
@@ -1277,70 +1285,54 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         }
       continue;
     }
+    // Per bin the tile touches (one, unless it straddles a bin edge), over the owned rows
+    // [q_lo, q_hi) in that bin: per offset column, the maximum of the lane's rows, then the
+    // lowest row that reaches it, one column at a time so few accumulators are live in VGPRs.
+    // Rows ascend with the bins, so the running (best, bestk) keeps the lowest row on ties.
     const int bA = (int)((kbase + r_lo) / nfd), bB = (int)((kbase + r_hi - 1) / nfd);
-    if (r_lo == 0 && r_hi == (32 * MB) && bA == bB) {
-      // whole tile owned and inside one bin
-      if (bA != cur_bin) {
-        if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
-        cur_bin = bA;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
-      }
-      // per offset column: tree maximum of the lane's 32 rows, then the lowest row that
-      // reaches it; one column at a time keeps few accumulators live in VGPRs.
+    auto reduce = [&](auto full, int q_lo, int q_hi) {
+      constexpr bool FULL = decltype(full)::value;
+      const unsigned span = (unsigned)(q_hi - q_lo);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        float mx = 0.0f;
-#pragma unroll
-        for (int t = 0; t < MB; ++t)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fabsf(acc[t][j][v]));
-        int row = 0;
-#pragma unroll
-        for (int t = MB - 1; t >= 0; --t)
-#pragma unroll
-          for (int v = 15; v >= 0; --v)
-            row = fabsf(acc[t][j][v]) == mx ? 32 * t + 8 * (v >> 2) + 4 * h + (v & 3) : row;
-        const bool gt = mx > best[j];
-        best[j] = gt ? mx : best[j];
-        bestk[j] = gt ? (int)kbase + row : bestk[j];
-        binmax[j] = fmaxf(binmax[j], mx);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
+        float mx = -1.0f;
 #pragma unroll
         for (int t = 0; t < MB; ++t)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
             const float a = fabsf(acc[t][j][v]);
-            const bool gt = row >= r_lo && row < r_hi && a > best[j];
-            best[j] = gt ? a : best[j];
-            bestk[j] = gt ? (int)kbase + row : bestk[j];
+            if constexpr (FULL) mx = fmaxf(mx, a);
+            else mx = (unsigned)(row - q_lo) < span ? fmaxf(mx, a) : mx;
           }
-      for (int bn = bA; bn <= bB; ++bn) {
-        if (bn != cur_bin) {
-          if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
-          cur_bin = bn;
+        int row = 0;
 #pragma unroll
-          for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
-        }
-        const int64_t e_lo = (int64_t)bn * nfd - kbase, e_hi = (int64_t)(bn + 1) * nfd - kbase;
-        const int q_lo = (int)(e_lo > r_lo ? e_lo : r_lo);
-        const int q_hi = (int)(e_hi < r_hi ? e_hi : r_hi);
+        for (int t = MB - 1; t >= 0; --t)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-          for (int t = 0; t < MB; ++t)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
-              const float a = fabsf(acc[t][j][v]);
-              binmax[j] = (row >= q_lo && row < q_hi) ? fmaxf(binmax[j], a) : binmax[j];
-            }
+          for (int v = 15; v >= 0; --v) {
+            const int r = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
+            const bool hit = fabsf(acc[t][j][v]) == mx && (FULL || (unsigned)(r - q_lo) < span);
+            row = hit ? r : row;
+          }
+        const bool gt = mx > best[j];   // false when no row is owned (mx = -1)
+        best[j] = gt ? mx : best[j];
+        bestk[j] = gt ? (int)kbase + row : bestk[j];
+        binmax[j] = fmaxf(binmax[j], mx);
+        __builtin_amdgcn_sched_barrier(0);
       }
+    };
+    for (int bn = bA; bn <= bB; ++bn) {
+      if (bn != cur_bin) {
+        if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
+        cur_bin = bn;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) binmax[j] = 0.0f;
+      }
+      const int64_t e_lo = (int64_t)bn * nfd - kbase, e_hi = (int64_t)(bn + 1) * nfd - kbase;
+      const int q_lo = (int)(e_lo > r_lo ? e_lo : r_lo);
+      const int q_hi = (int)(e_hi < r_hi ? e_hi : r_hi);
+      if (q_lo == 0 && q_hi == 32 * MB) reduce(BoolC<true>{}, 0, 32 * MB);
+      else reduce(BoolC<false>{}, q_lo, q_hi);
     }
     if constexpr (MODE == MODE_SIGMA) {
       // Sum of rho^2 over this wave's offsets for each owned row: per lane over its NB
