@@ -110,7 +110,9 @@ def fft_roofline(res, p, bf):
             "kernel_ms": round(ms, 3), "fft_points": 2 * m, "valid_per_block": valid}
 
 
-def roofline(res, p, prec, tile):
+def roofline(res, p, prec, tile, with_traffic=True):
+    """k_main against its MFMA peak.  `traffic` comes from the committed counter summary of
+    the strain workload, so other workloads pass with_traffic=False."""
     if prec == "fft":
         return fft_roofline(res, p, None)
     ms = res["kernel_ms"]["main"]
@@ -118,10 +120,36 @@ def roofline(res, p, prec, tile):
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": recorded_traffic(prec, tile),
+            "frac": round(achieved / peak, 4),
+            "traffic": recorded_traffic(prec, tile) if with_traffic else None,
             "kernel": "k_main", "kernel_ms": round(ms, 3),
             "mfma_terms": MFMA_TERMS[prec],
-            "executed_frac": round(achieved * MFMA_TERMS[prec] / peak, 4)}
+            "executed_frac": round(achieved * MFMA_TERMS[prec] / peak, 4),
+            # correlations/s x 2L against the FP32 MFMA peak: the like-for-like speed-up
+            "effective_vs_fp32_peak": round(achieved / PEAK_TFLOPS["fp32"], 3)}
+
+
+def lightcurve_leg(bf, torch, forms, steps):
+    """One GPU's share of the 8.64M-template light-curve bank: 720,000 templates of L = 2000
+    against the 64 s Kolmogorov-envelope photon-count series and its time-randomised control
+    (2 x 126,001 offsets), one batch per step.  Timing only; parity on this workload is a
+    GPU test."""
+    from synth import bank_params, cfg3_series
+    p3 = bank_params(3)
+    xs = [torch.from_numpy(cfg3_series()).cuda(), torch.from_numpy(cfg3_series(control=True)).cuda()]
+    out = {}
+    for form, n in forms:
+        log(f"light-curve share: {form}, 1 warmup + {n} steps")
+        r = time_form(bf, torch, p3, xs, form, n, 1)
+        out[form] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "steps": n,
+                     "roofline": roofline(r, p3, form, kernel_tile(form), with_traffic=False)}
+        log(f"  {r['value']:.4g} corr/s, {r['ms_per_step']:.1f} ms/step")
+        del r
+        torch.cuda.synchronize()
+    return {"workload": "light-curve bank share: 64 s photon counts (0.5 ms bins, 2000/s, "
+                        "Kolmogorov envelope) + time-randomised control; shard 0/12 of "
+                        "2880 f0 x 3000 fdot = 720,000 templates, L = 2000",
+            "correlations_per_step": 2 * 126001 * p3.K, "forms": out}
 
 
 def cpu_baseline(p, x64, xc64, n_off):
@@ -301,6 +329,8 @@ def main() -> int:
     ap.add_argument("--extra-forms", default="bf16x3,f16f8,f16x2,fft",
                     help="comma-separated further precision forms to time and check ('' skips)")
     ap.add_argument("--cpu-offsets", type=int, default=16384, help="0 skips the oracle leg")
+    ap.add_argument("--lightcurve", type=int, default=1,
+                    help="time the light-curve bank share too (0 skips it)")
     ap.add_argument("--serve-segments", type=int, default=16,
                     help="segments per point of the serving leg (0 skips it)")
     ap.add_argument("--serve-precision", default="bf16x3",
@@ -354,6 +384,15 @@ def main() -> int:
         log(f"timing {form}: 1 warmup + {args.fp32_steps} steps")
         extra[form] = time_form(bf, torch, p, xs, form, args.fp32_steps, 1)
         log(f"  {extra[form]['value']:.4g} corr/s, {extra[form]['ms_per_step']:.1f} ms/step")
+
+    lightcurve = None
+    if args.lightcurve:
+        lightcurve = lightcurve_leg(bf, torch, [(args.precision, 2), ("bf16x3", 2), ("fp32", 1)]
+                                    if args.precision not in ("bf16x3", "fp32")
+                                    else [(args.precision, 2), ("fp32", 1)], 2)
+        if "fp32" in lightcurve["forms"] and args.precision in lightcurve["forms"]:
+            lightcurve["speedup_of_chosen_form"] = (lightcurve["forms"][args.precision]["value"] /
+                                                    lightcurve["forms"]["fp32"]["value"])
 
     tails = None
     if args.tails_kappa > 0:
@@ -431,6 +470,7 @@ def main() -> int:
         "tails": tails,
         "error_vs_fp64": err or None,
         "cpu_baseline": cpu,
+        "lightcurve_share": lightcurve,
         "serving": serving,
         "serving_other_forms": serving_other or None,
     }
