@@ -284,12 +284,16 @@ def kernel_tile(prec):
 def recorded_traffic(prec, tile):
     """HBM bytes per launch of the contraction kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes, scaled by the same counters on a copy of known
-    size), if it was taken on exactly the current kernel source and tile; else None."""
+    size), if it was taken on exactly the current kernel source and tile; else None.  The
+    hash covers the kernel file followed by the internal header it includes."""
     import glob
     import hashlib
     kernel_file = "bfly_fft.hip" if prec == "fft" else "bfly_kernels.hip"
-    src = os.path.join(ROOT, "paper_1802_01685_amd", "csrc", kernel_file)
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    csrc = os.path.join(ROOT, "paper_1802_01685_amd", "csrc")
+    h = hashlib.sha256()
+    for name in (kernel_file, "bfly_internal.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    sha = h.hexdigest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
             if not line.startswith("traffic-record:"):

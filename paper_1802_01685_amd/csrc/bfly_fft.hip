@@ -270,7 +270,7 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_bank(GridDev g, BankDev b,
 // Data spectra: one work-group per (series, block) tile, persistent over the batch's tiles.
 template <int M>
 __global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restrict__ hdr,
-                                                          BankDev b) {
+                                                          BankDev b, int norm) {
   constexpr int T = Plan<M>::T;
   __shared__ float2 buf[Padded<M>::n];
   const SegDesc* segs = hdr_segs(hdr);
@@ -284,11 +284,17 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restr
     }
     const SegDesc& sg = segs[lo];
     const int64_t tau0 = (tt - sg.tile0) * valid;
+    // x - c0 (see series_offset); padding past the end and non-finite samples stage as 0, so
+    // a constant level does not enter the block's norm and with it the transform's rounding
+    const float c0 = series_offset(sg, norm);
+    auto xs = [&](int64_t gi) -> float {
+      if (gi >= sg.n) return 0.0f;
+      const float v = sg.x[gi];
+      return isfinite(v) ? v - c0 : 0.0f;
+    };
     for (int n = threadIdx.x; n < M; n += T) {
-      const int64_t i0 = tau0 + 2 * n, i1 = i0 + 1;
-      float a = i0 < sg.n ? sg.x[i0] : 0.0f;
-      float c = i1 < sg.n ? sg.x[i1] : 0.0f;
-      buf[pad(n)] = make_float2(isfinite(a) ? a : 0.0f, isfinite(c) ? c : 0.0f);
+      const int64_t i0 = tau0 + 2 * n;
+      buf[pad(n)] = make_float2(xs(i0), xs(i0 + 1));
     }
     __syncthreads();
     rfft_post<M>(buf, sg.xspec + (tt - sg.tile0) * (int64_t)(M + 2));
@@ -546,7 +552,7 @@ hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsi
 template <int M>
 hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                const SearchDev& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
+  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b, p.norm);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (fft_occupancy() == 4)

@@ -94,6 +94,27 @@ struct SegDesc {
   int64_t tail_cap;
 };
 
+// The level subtracted from every staged sample.  Under the centred normalisation (norm 0) it
+// is the mean of the series over its finite samples, from its prefix sums, rounded to a
+// multiple of q = 2^floor(log2 sigma), sigma the series' standard deviation: a mean within
+// about one sigma of zero gives 0, so data that the forms hold exactly (a run of zeros) stays
+// exact, while a level far above the fluctuations is removed.  With zero-mean templates the
+// correlation does not depend on a constant, and the rounding of each form then acts on the
+// fluctuations.  Under the raw normalisation (which includes the level) and for a series with
+// no finite samples or no spread it is 0.
+__device__ inline float series_offset(const SegDesc& sg, int norm) {
+  if (norm != 0) return 0.0f;
+  const int64_t good = sg.n - (int64_t)sg.cnt[sg.n];
+  if (good <= 0) return 0.0f;
+  const double mean = (sg.pre[4 * sg.n] + sg.pre[4 * sg.n + 1]) / (double)good;
+  const double var = (sg.pre[4 * sg.n + 2] + sg.pre[4 * sg.n + 3]) / (double)good - mean * mean;
+  if (!(var > 0.0)) return 0.0f;
+  int e;
+  frexp(sqrt(var), &e);             // sigma in [2^(e-1), 2^e)
+  const double q = ldexp(1.0, e - 1);
+  return (float)(rint(mean / q) * q);
+}
+
 // Header of a batch table in device memory: the table is [BatchHdr][SegDesc x n_segs].  The
 // kernels read the batch sizes from it, so one captured launch sequence (grids sized for the
 // largest batch, the contraction kernel looping over its work items) serves any batch.

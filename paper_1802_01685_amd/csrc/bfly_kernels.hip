@@ -878,15 +878,24 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int64_t tile_hi = (k_hi + (32 * MB) - 1) / (32 * MB);
 
   // ---- strip fill ----
+  // Every form stages x - c, c the level from series_offset (the series mean under the centred
+  // normalisation): the correlation does not depend on c, and the rounding then acts on the
+  // fluctuations, not on a constant level.
+  // Padding past the series end and non-finite samples stage as 0 in this shifted frame: they
+  // reach only masked offsets, and a -c there would set the strip scale instead of the data.
+  const float c0 = series_offset(sg, p.norm);
+  auto xs = [&](int64_t gi) -> float {
+    if (gi >= sg.n) return 0.0f;
+    const float v = sg.x[gi];
+    return isfinite(v) ? v - c0 : 0.0f;
+  };
   const int S = (32 * NB * WG_WAVES) + b.L_pad + STRIP_SLACK;  // multiple of 8
   int sb = 127;          // FP8, F16F8, F16F6: E8M0 scale of the strip's codes (per lane)
   float dscale = 1.0f;   // F16X2, F16F8, F16F6: 2^-(10 + e_x), undoing both power-of-two scales
   if constexpr (PREC == P_FP32) {
     float* sx = (float*)lds;
     for (int i = tid; i < S; i += WG_THREADS) {
-      const int64_t gi = tau0 + i;
-      float v = gi < sg.n ? sg.x[gi] : 0.0f;
-      sx[i] = isfinite(v) ? v : 0.0f;
+      sx[i] = xs(tau0 + i);
     }
   } else if constexpr (PREC == P_FP8 || PREC == P_F16X2 || is_f16r(PREC)) {
     // strip scale 2^e_x: the largest power of two keeping max |x| over the strip <= LIM
@@ -895,9 +904,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     __shared__ float wmax[WG_WAVES];
     float mx = 0.0f;
     for (int i = tid; i < S; i += WG_THREADS) {
-      const int64_t gi = tau0 + i;
-      const float v = gi < sg.n ? sg.x[gi] : 0.0f;
-      if (isfinite(v)) mx = fmaxf(mx, fabsf(v));
+      mx = fmaxf(mx, fabsf(xs(tau0 + i)));
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
@@ -915,9 +922,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         float v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int64_t gi = tau0 + 8 * q + c + e;
-          float u = gi < sg.n ? sg.x[gi] : 0.0f;
-          v[e] = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+          v[e] = ldexpf(xs(tau0 + 8 * q + c + e), ex);
         }
         int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
         w0 = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w0, true);
@@ -940,9 +945,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         float yh[8], yl[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int64_t gi = tau0 + t + e;
-          const float u = gi < sg.n ? sg.x[gi] : 0.0f;
-          const float y = isfinite(u) ? ldexpf(u, ex) : 0.0f;
+          const float y = ldexpf(xs(tau0 + t + e), ex);
           yh[e] = (float)(_Float16)y;
           yl[e] = y - yh[e];
         }
@@ -991,7 +994,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
           iv = sg.inv_norm[tau];
           const double* a = sg.pre + tau * 4;
           const double* z = sg.pre + (tau + b.L) * 4;
-          m = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L) / dscale;
+          m = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L - (double)c0) / dscale;
         }
         inv_l[i] = iv;
         mu_l[i] = m;
@@ -1004,9 +1007,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         _Float16 hv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t gi = tau0 + 4 * q + c + e;
-          float u = gi < sg.n ? sg.x[gi] : 0.0f;
-          hv[e] = (_Float16)(isfinite(u) ? ldexpf(u, ex) : 0.0f);
+          hv[e] = (_Float16)ldexpf(xs(tau0 + 4 * q + c + e), ex);
         }
         *(uint2*)(lds + t * 8) = __builtin_bit_cast(uint2, hv);
       }
@@ -1019,9 +1020,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       uint32_t hw[2] = {0u, 0u}, lw[2] = {0u, 0u};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t gi = tau0 + 4 * q + c + e;
-        float v = gi < sg.n ? sg.x[gi] : 0.0f;
-        v = isfinite(v) ? v : 0.0f;
+        const float v = xs(tau0 + 4 * q + c + e);
         const uint32_t hb = bf16_bits(v);
         const float hv = __uint_as_float(hb << 16);
         const uint32_t lb = bf16_bits(v - hv);
@@ -1059,7 +1058,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       if (tau < sg.W) {
         const double* a = sg.pre + tau * 4;
         const double* z = sg.pre + (tau + b.L) * 4;
-        mu[j] = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L);
+        mu[j] = (float)(((z[0] - a[0]) + (z[1] - a[1])) / (double)b.L - (double)c0);
       }
     }
   }

@@ -45,6 +45,21 @@ def _run(bf, p, x32, prec, t_block=1, norm="centred", hist_bins=256, lo=0.0, hi=
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("offset", [1000.0, -250.0])
+def test_constant_offset(bf, prec, offset):
+    """The centred correlation does not depend on a constant added to the series (an
+    invariant the oracle pins); every form stays within its tolerance when the 4 s, 512 Hz
+    unit-variance strain-like series is raised or lowered far past its fluctuations."""
+    p = bank_params(1)
+    x32 = (cfg1_series() + offset).astype(np.float32)
+    x64 = x32.astype(np.float64)
+    g, _ = _run(bf, p, x32, prec)
+    orc = O.search(x64, p)
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"offset {offset}/{prec}")
+    print(f"offset {offset} {prec}: {st}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_cfg1_full(bf, prec):
     """4 s at 512 Hz, bank 16x16, L = 512: every one of the 1537 offsets."""
     p = bank_params(1)
