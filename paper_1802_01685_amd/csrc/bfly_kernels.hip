@@ -438,9 +438,9 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 // ---------------------------------------------------------------------------------------
 // The contraction with the fused reductions.
 //
-// Work item = (series, offset tile of n_wg = 128*NB offsets, bin range).  Items are numbered
-// range-fastest and the planner uses a multiple of 8 ranges, so each XCD's work-groups sweep
-// only their own part of the bank, in step, and share it through that XCD's L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + n_wg + L_pad) (zero
+// Work item = (series, offset tile of n_wg = 128*NB offsets, bin range).  The planner uses a
+// multiple of 8 ranges and the items are numbered so that each XCD's work-groups sweep only
+// their own ranges, one at a time, in step, and share each through that XCD's L2.  A work-group fills an LDS strip with x[tau0 .. tau0 + n_wg + L_pad) (zero
 // past the end; non-finite samples as 0 -- their windows are degenerate and discarded),
 // then each wave sweeps the item's template tiles: for each tile, a full K-loop over the
 // taps into MB x NB accumulators of 32 x 32, then the epilogue.
@@ -849,6 +849,8 @@ struct BoolC {
 
 // One work item: strip fill, template sweep, flushes.  PIPE selects the K-loop schedule,
 // MODE the pass (MainMode).
+constexpr int N_XCD = 8;   // XCDs of the MI355X; work-groups are dealt to them round robin
+
 template <int PREC, int MB, int NB, int PIPE, int MODE>
 __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int64_t item,
                                           const BankDev& b, const SearchDev& p, char* lds) {
@@ -859,10 +861,21 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int n_ranges = hdr->n_ranges;
 
   // ---- which item ----
-  // Bin range fastest: work-group i runs on XCD i mod 8, so with a multiple of 8 ranges
-  // each XCD only ever sweeps its own ranges and the bank streams into each L2 once.
-  const int r = (int)(item % n_ranges);
-  const int64_t tt = item / n_ranges;
+  // Work-group i runs on XCD i mod 8 and each XCD takes its work-groups in order of i / 8.
+  // With 8m ranges, XCD x sweeps its ranges x, x + 8, ..., x + 8(m - 1) one after another,
+  // offset tiles fastest: the work-groups resident on an XCD at any time sweep one range in
+  // step and share it through that XCD's L2 (with m = 1 this is range-fastest numbering).
+  // Fewer than 8 ranges (fewer than 8 bins): range fastest.
+  int r;
+  int64_t tt;
+  if (n_ranges % N_XCD == 0) {
+    const int64_t j = item / N_XCD;
+    r = (int)(item % N_XCD) + N_XCD * (int)(j / total_tiles);
+    tt = j % total_tiles;
+  } else {
+    r = (int)(item % n_ranges);
+    tt = item / n_ranges;
+  }
   int lo = 0, hi = hdr->n_segs - 1;
   while (lo < hi) {  // last series with tile0 <= tt
     const int mid = (lo + hi + 1) >> 1;
