@@ -77,10 +77,10 @@ typedef enum {
                     with power-of-two scales (per template, per strip) undone by the MFMA scale
                     operands; the rounded templates' sums times the window mean are
                     subtracted.  Two thirds of BF_BF16X3's MFMA time per tap; ~1e-5 to 3e-5
-                    relative error, stated bound 1e-4; L <= 5248 */
+                    relative error, stated bound 1e-4; L <= 4224 */
   BF_F16F6 = 6   /* as BF_F16F8 with the residual products in e2m3 (fp6) codes, whose MFMA
                     runs at twice the e4m3 rate: half of BF_BF16X3's MFMA time per tap.
-                    Stated bound 1e-4; L <= 5248 */
+                    Stated bound 1e-4; L <= 4224 */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;

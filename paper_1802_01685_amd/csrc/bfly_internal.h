@@ -22,7 +22,7 @@ constexpr int KCH_F16F8 = 32;                 // taps per chunk, F16F8 form
 constexpr int STRIP_SLACK = 16;               // extra strip samples past N_WG + L_pad
 constexpr int MAX_L = 8192;
 constexpr int MAX_FFT_L = 4096;              // FFT form: N = 2M <= 8192
-constexpr int MAX_F16F8_L = 5248;            // F16F8, F16F6: 24-byte strip cells + 12 KB
+constexpr int MAX_F16F8_L = 4224;            // F16F8, F16F6: 24-byte strip cells + 36 KB
                                              // fill 160 KB LDS
 constexpr int MAX_HIST_BINS = 4096;
 constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums

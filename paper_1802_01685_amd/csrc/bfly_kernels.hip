@@ -462,8 +462,8 @@ __global__ __launch_bounds__(256) void k_norms(const BatchHdr* __restrict__ hdr,
 size_t main_lds_bytes(int precision, int L_pad, int n_wg) {
   const size_t S = (size_t)n_wg + (size_t)L_pad + STRIP_SLACK;
   // F16F8, F16F6: fp16 plane + two code planes, then the item's 1/sqrt(E) (double) and window
-  // means (float)
-  if (is_f16r(precision)) return S * 24 + (size_t)n_wg * 12;
+  // means (float), then the waves' running maxima between tiles (3 words per offset)
+  if (is_f16r(precision)) return S * 24 + (size_t)n_wg * 36;
   return precision == P_FP32 ? S * 4 : (precision == P_FP8 || precision == P_F16X2) ? S * 8 : S * 16;
 }
 
@@ -1083,6 +1083,38 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     bestk[j] = -1;
     binmax[j] = 0.0f;
   }
+  // F16F8, F16F6: their K-loop needs every register, so between tiles the running maxima
+  // wait in LDS (per wave [best | bestk | binmax][NB][64 lanes], after the window means)
+  // instead of in scratch.  The address is hidden from the compiler so that it reloads them
+  // after each K-loop rather than keeping them live across it.
+  const int st_addr = 3 * plane_bytes + 32 * NB * WG_WAVES * 12 + (wave * 3 * NB * 64 + lane) * 4;
+  auto park = [&]() {
+    if constexpr (is_f16r(PREC)) {
+      int a = st_addr;
+      asm volatile("" : "+v"(a));
+      float* st = (float*)(lds + a);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        st[64 * j] = best[j];
+        st[64 * (NB + j)] = __int_as_float(bestk[j]);
+        st[64 * (2 * NB + j)] = binmax[j];
+      }
+    }
+  };
+  auto unpark = [&]() {
+    if constexpr (is_f16r(PREC)) {
+      int a = st_addr;
+      asm volatile("" : "+v"(a));
+      const float* st = (const float*)(lds + a);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        best[j] = st[64 * j];
+        bestk[j] = __float_as_int(st[64 * (NB + j)]);
+        binmax[j] = st[64 * (2 * NB + j)];
+      }
+    }
+  };
+  park();
   int cur_bin = -1;
   const int nfd = b.n_fdot;
 
@@ -1270,7 +1302,10 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     if constexpr (MODE == MODE_TAILS) {
       // rho = d / sqrt(E) exactly as the butterfly output is formed; every owned (tau, k)
       // with |rho| > kappa * sigma_k is appended to the series' list and counted in its bin.
+      // (rows as in the search epilogue: c + 4h, the ownership test on the immediate c)
       const float* th = sg.thr + kbase + 4 * h;
+      const int qh = r_lo - 4 * h;
+      const unsigned span = (unsigned)(r_hi - r_lo);
 #pragma unroll
       for (int t = 0; t < MB; ++t)
 #pragma unroll
@@ -1281,10 +1316,10 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
           for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int row = 32 * t + 8 * g + 4 * h + i;
+              const int c = 32 * t + 8 * g + i;
               const float rf = (float)((double)(acc[t][j][4 * g + i] * dscale) * inv[j]);
-              if (fabsf(rf) > tv[i] && row >= r_lo && row < r_hi) {
-                const int64_t kl = kbase + row;
+              if (fabsf(rf) > tv[i] && (unsigned)(c - qh) < span) {
+                const int64_t kl = kbase + c + 4 * h;
                 const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
                 if ((int64_t)slot < sg.tail_cap) {
                   sg.t_tau[slot] = (int32_t)(tau_w0 + 32 * j + n);
@@ -1297,14 +1332,19 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         }
       continue;
     }
+    unpark();
     // Per bin the tile touches (one, unless it straddles a bin edge), over the owned rows
     // [q_lo, q_hi) in that bin: per offset column, the maximum of the lane's rows, then the
     // lowest row that reaches it, one column at a time so few accumulators are live in VGPRs.
     // Rows ascend with the bins, so the running (best, bestk) keeps the lowest row on ties.
     const int bA = (int)((kbase + r_lo) / nfd), bB = (int)((kbase + r_hi - 1) / nfd);
+    // Row of accumulator v of block t: c + 4h with c = 32t + 8(v >> 2) + (v & 3); the search
+    // runs on the lane-independent c (immediates, so no per-lane row table is kept live
+    // across the K-loop) and adds 4h once.
     auto reduce = [&](auto full, int q_lo, int q_hi) {
       constexpr bool FULL = decltype(full)::value;
       const unsigned span = (unsigned)(q_hi - q_lo);
+      const int qh = q_lo - 4 * h;   // row - q_lo = c - qh
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         float mx = -1.0f;
@@ -1312,20 +1352,21 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         for (int t = 0; t < MB; ++t)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int row = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
+            const int c = 32 * t + 8 * (v >> 2) + (v & 3);
             const float a = fabsf(acc[t][j][v]);
             if constexpr (FULL) mx = fmaxf(mx, a);
-            else mx = (unsigned)(row - q_lo) < span ? fmaxf(mx, a) : mx;
+            else mx = (unsigned)(c - qh) < span ? fmaxf(mx, a) : mx;
           }
         int row = 0;
 #pragma unroll
         for (int t = MB - 1; t >= 0; --t)
 #pragma unroll
           for (int v = 15; v >= 0; --v) {
-            const int r = 32 * t + 8 * (v >> 2) + 4 * h + (v & 3);
-            const bool hit = fabsf(acc[t][j][v]) == mx && (FULL || (unsigned)(r - q_lo) < span);
-            row = hit ? r : row;
+            const int c = 32 * t + 8 * (v >> 2) + (v & 3);
+            const bool hit = fabsf(acc[t][j][v]) == mx && (FULL || (unsigned)(c - qh) < span);
+            row = hit ? c : row;
           }
+        row += 4 * h;
         const bool gt = mx > best[j];   // false when no row is owned (mx = -1)
         best[j] = gt ? mx : best[j];
         bestk[j] = gt ? (int)kbase + row : bestk[j];
@@ -1382,7 +1423,9 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
         if (f) atomicAdd(sg.sig_acc + kbase + row, f);
       }
     }
+    park();
   }
+  unpark();
   if (cur_bin >= 0) flush_bin<NB>(sg, b, p, cur_bin, binmax, inv, tau_w0, n, h, lane, dscale);
 
   // ---- per-offset maxima: combine the two row halves, then one atomic per offset ----

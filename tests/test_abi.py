@@ -63,15 +63,15 @@ def test_bank_bytes_and_validation_on_host(lib):
     # (multiple of 64) for L = 2000; L is capped by the strip's LDS footprint
     dm = lib.make_desc(bank_params(3), "f16f8")
     assert lib.bank_bytes(dm) == 720000 * 2048 * 4 + 720000 * 8 + 256
-    dm.L = 5249
+    dm.L = 4225
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(dm)
-    dm.L = 5248
-    assert lib.bank_bytes(dm) == 720000 * 5248 * 4 + 720000 * 8 + 256
+    dm.L = 4224
+    assert lib.bank_bytes(dm) == 720000 * 4224 * 4 + 720000 * 8 + 256
     # F16F6: fp16 (2 bytes) + two 6-bit codes per tap = 3.5 bytes, the same side tables
     d6 = lib.make_desc(bank_params(3), "f16f6")
     assert lib.bank_bytes(d6) == 720000 * 2048 * 7 // 2 + 720000 * 8 + 256
-    d6.L = 5249
+    d6.L = 4225
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(d6)
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
