@@ -314,10 +314,15 @@ hipError_t launch_zero(const BatchHdr* hdr, int32_t seg_slots, int32_t x_blocks,
 }
 
 // ---------------------------------------------------------------------------------------
-// Prefix sums: one 1024-thread work-group per series scans x in tiles of 1024 samples,
-// carrying double-double sums of x and x^2 (non-finite samples count as 0 and are
-// counted separately).  pre[i] holds the sums over x[0..i).
+// Prefix sums: one 1024-thread work-group per series scans x in tiles of 1024 x PRE_E
+// samples, carrying double-double sums of x and x^2 (non-finite samples count as 0 and are
+// counted separately).  pre[i] holds the sums over x[0..i).  Each thread sums its PRE_E
+// consecutive samples, the threads' totals are scanned across the wave by shuffles and
+// across the 16 waves by thread 0, and each thread then runs through its samples again
+// (from cache) from the sum of everything before them, writing each prefix.
 // ---------------------------------------------------------------------------------------
+constexpr int PRE_E = 16;
+
 __global__ __launch_bounds__(1024) void k_prefix(const BatchHdr* __restrict__ hdr) {
   if ((int)blockIdx.x >= hdr->n_segs) return;
   const SegDesc& sg = hdr_segs(hdr)[blockIdx.x];
@@ -337,58 +342,90 @@ __global__ __launch_bounds__(1024) void k_prefix(const BatchHdr* __restrict__ hd
     sg.cnt[0] = 0;
   }
   __syncthreads();
-  for (int64_t base = 0; base < sg.n; base += 1024) {
-    const int64_t i = base + tid;
-    const float v = i < sg.n ? sg.x[i] : 0.0f;
-    const bool fin = isfinite(v);
-    const double a = fin ? (double)v : 0.0;
-    dd s1 = {a, 0.0}, s2 = {a * a, 0.0};  // a*a is exact for a float a
-    int c = (i < sg.n && !fin) ? 1 : 0;
+  for (int64_t base = 0; base < sg.n; base += 1024 * PRE_E) {
+    const int64_t i0 = base + (int64_t)tid * PRE_E;
+    // this thread's totals over its PRE_E samples
+    dd s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
+    int c = 0;
+#pragma unroll
+    for (int e = 0; e < PRE_E; ++e) {
+      const int64_t i = i0 + e;
+      const float v = i < sg.n ? sg.x[i] : 0.0f;
+      const bool fin = isfinite(v);
+      const double a = fin ? (double)v : 0.0;
+      s1 = dd_add(s1, {a, 0.0});
+      s2 = dd_add(s2, {a * a, 0.0});  // a*a is exact for a float a
+      c += (i < sg.n && !fin) ? 1 : 0;
+    }
+    // inclusive scan of the thread totals across the wave
+    dd t1 = s1, t2 = s2;
+    int tc = c;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const dd t1 = {__shfl_up(s1.hi, off, 64), __shfl_up(s1.lo, off, 64)};
-      const dd t2 = {__shfl_up(s2.hi, off, 64), __shfl_up(s2.lo, off, 64)};
-      const int tc = __shfl_up(c, off, 64);
+      const dd u1 = {__shfl_up(t1.hi, off, 64), __shfl_up(t1.lo, off, 64)};
+      const dd u2 = {__shfl_up(t2.hi, off, 64), __shfl_up(t2.lo, off, 64)};
+      const int uc = __shfl_up(tc, off, 64);
       if (lane >= off) {
-        s1 = dd_add(t1, s1);
-        s2 = dd_add(t2, s2);
-        c += tc;
+        t1 = dd_add(u1, t1);
+        t2 = dd_add(u2, t2);
+        tc += uc;
       }
     }
+    // exclusive: the inclusive scan of the previous lane (0 on lane 0)
+    dd x1 = {__shfl_up(t1.hi, 1, 64), __shfl_up(t1.lo, 1, 64)};
+    dd x2 = {__shfl_up(t2.hi, 1, 64), __shfl_up(t2.lo, 1, 64)};
+    int xc = __shfl_up(tc, 1, 64);
+    if (lane == 0) {
+      x1 = {0.0, 0.0};
+      x2 = {0.0, 0.0};
+      xc = 0;
+    }
     if (lane == 63) {
-      w1[wave] = s1;
-      w2[wave] = s2;
-      wc[wave] = c;
+      w1[wave] = t1;
+      w2[wave] = t2;
+      wc[wave] = tc;
     }
     __syncthreads();
     if (tid == 0) {
       dd r1 = c1s, r2 = c2s;
       int rc = ccs;
       for (int w = 0; w < 16; ++w) {
-        const dd t1 = w1[w], t2 = w2[w];
-        const int tc = wc[w];
+        const dd a1 = w1[w], a2 = w2[w];
+        const int ac = wc[w];
         w1[w] = r1;
         w2[w] = r2;
         wc[w] = rc;
-        r1 = dd_add(r1, t1);
-        r2 = dd_add(r2, t2);
-        rc += tc;
+        r1 = dd_add(r1, a1);
+        r2 = dd_add(r2, a2);
+        rc += ac;
       }
       c1s = r1;
       c2s = r2;
       ccs = rc;
     }
     __syncthreads();
-    s1 = dd_add(w1[wave], s1);
-    s2 = dd_add(w2[wave], s2);
-    c += wc[wave];
-    if (i < sg.n) {
-      double* o = sg.pre + (i + 1) * 4;
-      o[0] = s1.hi;
-      o[1] = s1.lo;
-      o[2] = s2.hi;
-      o[3] = s2.lo;
-      sg.cnt[i + 1] = c;
+    // everything before this thread's first sample: the carry and earlier waves (from
+    // LDS), then the earlier threads of this wave
+    dd q1 = dd_add(w1[wave], x1);
+    dd q2 = dd_add(w2[wave], x2);
+    int qc = wc[wave] + xc;
+#pragma unroll
+    for (int e = 0; e < PRE_E; ++e) {
+      const int64_t i = i0 + e;
+      if (i < sg.n) {
+        const float v = sg.x[i];
+        const bool fin = isfinite(v);
+        const double a = fin ? (double)v : 0.0;
+        q1 = dd_add(q1, {a, 0.0});
+        q2 = dd_add(q2, {a * a, 0.0});
+        qc += fin ? 0 : 1;
+        double* o = sg.pre + (i + 1) * 4;
+        o[0] = q1.hi;
+        o[1] = q1.lo;
+        o[2] = q2.hi;
+        o[3] = q2.lo;
+        sg.cnt[i + 1] = qc;
+      }
     }
     __syncthreads();
   }
