@@ -134,9 +134,9 @@ def lightcurve_leg(bf, torch, forms, steps):
     against the 64 s Kolmogorov-envelope photon-count series and its time-randomised control
     (2 x 126,001 offsets), one batch per step.  Timing only; parity on this workload is a
     GPU test."""
-    from synth import bank_params, cfg3_series
-    p3 = bank_params(3)
-    xs = [torch.from_numpy(cfg3_series()).cuda(), torch.from_numpy(cfg3_series(control=True)).cuda()]
+    from synth import bank_params, light_curve_series
+    p3 = bank_params("light_curve_share")
+    xs = [torch.from_numpy(light_curve_series()).cuda(), torch.from_numpy(light_curve_series(control=True)).cuda()]
     out = {}
     for form, n in forms:
         log(f"light-curve share: {form}, 1 warmup + {n} steps")
@@ -217,14 +217,14 @@ def serving_leg(bf, prec, n_segments, budget_gib, slots):
     dominates latency), and the same trace with arrivals scaled to ~70% of the capacity
     measured on the first point.  Latency = submit to done, from the server's own clock."""
     import numpy as np
-    from synth import bank_params, cfg5_trace, cfg5_segment
-    p5 = bank_params(5)
+    from synth import bank_params, serving_trace, serving_segment
+    p5 = bank_params("serving")
     bank = bf.bank_create(p5, prec)
     prm = bf.make_params(t_block=256)
     srv = bf.server_create(bank, budget_gib << 30, max_slots=slots, ticks_in_flight=2, params=prm)
 
     def run(trace):
-        xs = [cfg5_segment(e) for e in trace]
+        xs = [serving_segment(e) for e in trace]
         t0 = time.perf_counter()
         a0 = trace[0]["t_arrival"]
         tickets = []
@@ -252,11 +252,11 @@ def serving_leg(bf, prec, n_segments, budget_gib, slots):
                 "correlations_per_s": corr / busy, "busy_s": busy,
                 "offered_segments_per_s": (len(trace) - 1) / max(trace[-1]["t_arrival"] - a0, 1e-9)}
 
-    literal = run(cfg5_trace(n_segments))
-    mean_corr = np.mean([bank.K * (e["n"] - p5.L + 1) for e in cfg5_trace(n_segments)])
+    literal = run(serving_trace(n_segments))
+    mean_corr = np.mean([bank.K * (e["n"] - p5.L + 1) for e in serving_trace(n_segments)])
     capacity = literal["correlations_per_s"] / mean_corr          # segments/s
     scale = 0.7 * capacity / 50.0
-    scaled = run(cfg5_trace(n_segments, rate_scale=scale))
+    scaled = run(serving_trace(n_segments, rate_scale=scale))
     scaled["rate_scale"] = scale
     stats = bf.server_stats(srv)
     bf.server_destroy(srv)
@@ -349,20 +349,20 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the multi-GPU bank-sharded search is a design "
-              "(max-loc all-reduce over the f0 shards), not part of this build.", file=sys.stderr)
+              "(max-loc all-reduce over the f0 shards), not implemented here.", file=sys.stderr)
         return 2
 
     import numpy as np
     import torch
     from paper_1802_01685_amd import bfly as bf
-    from synth import bank_params, cfg2_series, time_randomised
+    from synth import bank_params, strain_series, time_randomised
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     bf.lib()
-    p = bank_params(2)
-    x = cfg2_series()
+    p = bank_params("strain")
+    x = strain_series()
     xc = time_randomised(x, seed=102)
     xs = [torch.from_numpy(x).cuda(), torch.from_numpy(xc).cuda()]
     if args.copy_probe_mib > 0:

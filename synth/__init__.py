@@ -12,14 +12,14 @@ from .series import (  # noqa: F401
     kolmogorov_light_curve,
     time_randomised,
 )
-from .configs import (  # noqa: F401
+from .workloads import (  # noqa: F401
     BankParams,
     WORKLOADS,
     bank_params,
-    cfg1_series,
-    cfg2_series,
-    cfg3_series,
-    cfg4_batch,
-    cfg5_trace,
-    cfg5_segment,
+    small_strain_series,
+    strain_series,
+    light_curve_series,
+    light_curve_batch,
+    serving_trace,
+    serving_segment,
 )

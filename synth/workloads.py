@@ -1,8 +1,9 @@
 """The five workloads: bank parameters and seeded series, traces and controls.
 
-Seeds: the data seed of workload c is c, its control permutation seed 100 + c; workload 4
-draws per-series data seeds 400 + i and control seeds 1400 + i; workload 5 draws its
-arrival trace from seed 500 and each segment's noise from seed 5000 + i.
+Seeds: the small strain-like series draws its noise from seed 1, the 32 s strain-like series
+from seed 2 (control permutation seed 102), the 64 s light curve from seed 3 (control 103);
+the 42-light-curve batch draws per-series data seeds 400 + i and control seeds 1400 + i;
+the serving trace draws its arrivals from seed 500 and each segment's noise from 5000 + i.
 """
 
 from __future__ import annotations
@@ -56,38 +57,40 @@ class BankParams:
 
 
 _BANKS = {
-    1: BankParams(fs=512.0, L=512, n_f0=16, n_fdot=16, f0_min=20.0, f0_max=200.0,
-                  fdot_min=-100.0, fdot_max=100.0),
-    2: BankParams(fs=4096.0, L=4096, n_f0=256, n_fdot=256, f0_min=50.0, f0_max=2000.0,
-                  fdot_min=-2000.0, fdot_max=2000.0),
+    "small_strain": BankParams(fs=512.0, L=512, n_f0=16, n_fdot=16, f0_min=20.0,
+                               f0_max=200.0, fdot_min=-100.0, fdot_max=100.0),
+    "strain": BankParams(fs=4096.0, L=4096, n_f0=256, n_fdot=256, f0_min=50.0, f0_max=2000.0,
+                         fdot_min=-2000.0, fdot_max=2000.0),
     # One GPU's share of an 8.64M-template bank: 2880 f0 x 3000 fdot split 12 ways by f0.
-    3: BankParams(fs=2000.0, L=2000, n_f0=2880, n_fdot=3000, f0_min=10.0, f0_max=1000.0,
-                  fdot_min=-1000.0, fdot_max=1000.0, shard_index=0, shard_count=12),
-    4: BankParams(fs=2000.0, L=2000, n_f0=512, n_fdot=512, f0_min=10.0, f0_max=1000.0,
-                  fdot_min=-1000.0, fdot_max=1000.0),
-    5: BankParams(fs=4096.0, L=4096, n_f0=512, n_fdot=512, f0_min=50.0, f0_max=2000.0,
-                  fdot_min=-2000.0, fdot_max=2000.0),
+    "light_curve_share": BankParams(fs=2000.0, L=2000, n_f0=2880, n_fdot=3000, f0_min=10.0,
+                                    f0_max=1000.0, fdot_min=-1000.0, fdot_max=1000.0,
+                                    shard_index=0, shard_count=12),
+    "light_curve_batch": BankParams(fs=2000.0, L=2000, n_f0=512, n_fdot=512, f0_min=10.0,
+                                    f0_max=1000.0, fdot_min=-1000.0, fdot_max=1000.0),
+    "serving": BankParams(fs=4096.0, L=4096, n_f0=512, n_fdot=512, f0_min=50.0, f0_max=2000.0,
+                          fdot_min=-2000.0, fdot_max=2000.0),
 }
 
 WORKLOADS = {
-    1: "tiny: 4 s at 512 Hz, f64 white noise + chirp (60 Hz, +40 Hz/s, A=0.5, t=1.3 s); "
-       "bank 16x16 L=512",
-    2: "strain-like: 32 s at 4096 Hz, f32 white noise + chirp (100 Hz, +150 Hz/s, SNR 8, "
-       "t=12 s); bank 256x256 L=4096",
-    3: "light-curve bank share: 64 s Poisson counts in 0.5 ms bins, 2000/s, Kolmogorov "
-       "envelope; shard 0/12 of 2880x3000 (720,000 templates) L=2000; + shuffled control",
-    4: "batch: 42 light curves 20-200 s, 500-5000 counts/s, each + shuffled control; "
-       "bank 512x512 L=2000",
-    5: "serving: two-channel 4096 Hz strain segments 1-64 s, 30% with chirps, 50/s Poisson "
-       "arrivals; bank 512x512 L=4096",
+    "small_strain": "4 s at 512 Hz, f64 white noise + chirp (60 Hz, +40 Hz/s, A=0.5, "
+                    "t=1.3 s); bank 16x16 L=512",
+    "strain": "strain-like: 32 s at 4096 Hz, f32 white noise + chirp (100 Hz, +150 Hz/s, "
+              "SNR 8, t=12 s); bank 256x256 L=4096",
+    "light_curve_share": "light-curve bank share: 64 s Poisson counts in 0.5 ms bins, 2000/s, "
+                         "Kolmogorov envelope; shard 0/12 of 2880x3000 (720,000 templates) "
+                         "L=2000; + shuffled control",
+    "light_curve_batch": "batch: 42 light curves 20-200 s, 500-5000 counts/s, each + "
+                         "shuffled control; bank 512x512 L=2000",
+    "serving": "serving: two-channel 4096 Hz strain segments 1-64 s, 30% with chirps, 50/s "
+               "Poisson arrivals; bank 512x512 L=4096",
 }
 
 
-def bank_params(cfg: int) -> BankParams:
-    return _BANKS[cfg]
+def bank_params(workload: str) -> BankParams:
+    return _BANKS[workload]
 
 
-def cfg1_series() -> np.ndarray:
+def small_strain_series() -> np.ndarray:
     """2048 samples (4 s at 512 Hz), float64: unit white noise + 0.5 * chirp(60, +40) at 1.3 s."""
     x = white_noise(2048, seed=1)
     sig, _ = chirp_samples(2048, 512.0, start=1.3, f0=60.0, fdot=40.0)
@@ -101,7 +104,7 @@ def _snr_amplitude(fs: float, f0: float, fdot: float, snr: float) -> float:
     return snr / float(np.linalg.norm(c))
 
 
-def cfg2_series() -> np.ndarray:
+def strain_series() -> np.ndarray:
     """131072 samples (32 s at 4096 Hz), float32: unit noise + SNR-8 chirp(100, +150) at 12 s."""
     fs = 4096.0
     x = white_noise(131072, seed=2)
@@ -110,13 +113,13 @@ def cfg2_series() -> np.ndarray:
     return x.astype(np.float32)
 
 
-def cfg3_series(control: bool = False) -> np.ndarray:
+def light_curve_series(control: bool = False) -> np.ndarray:
     """128000 standardised photon-count bins (64 s at 0.5 ms), float32; or its control."""
     x = kolmogorov_light_curve(128000, rate=2000.0, seed=3)
     return time_randomised(x, seed=103) if control else x
 
 
-def cfg4_batch() -> list[dict]:
+def light_curve_batch() -> list[dict]:
     """42 light curves of 20-200 s at 500-5000 counts/s, each followed by its control.
 
     Returns 84 dicts {name, x, series, control} in the order data_0, control_0, data_1, ...
@@ -134,7 +137,7 @@ def cfg4_batch() -> list[dict]:
     return out
 
 
-def cfg5_trace(n_segments: int = 256, rate_scale: float = 1.0) -> list[dict]:
+def serving_trace(n_segments: int = 256, rate_scale: float = 1.0) -> list[dict]:
     """Seeded arrival trace: Poisson arrivals at 50/s (times ``rate_scale``).
 
     Each entry: arrival time (s), channel, n samples, and an optional chirp injection
@@ -157,7 +160,7 @@ def cfg5_trace(n_segments: int = 256, rate_scale: float = 1.0) -> list[dict]:
     return out
 
 
-def cfg5_segment(entry: dict) -> np.ndarray:
+def serving_segment(entry: dict) -> np.ndarray:
     """The float32 samples of one trace entry: unit noise (seed 5000+i) + optional chirp."""
     fs = 4096.0
     n = entry["n"]

@@ -43,25 +43,25 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_bank_bytes_and_validation_on_host(lib):
     from synth import bank_params
-    d = lib.make_desc(bank_params(2), "bf16x3")
+    d = lib.make_desc(bank_params("strain"), "bf16x3")
     # K_pad * L_pad * 4 bytes + a 256-byte status word
     assert lib.bank_bytes(d) == 65536 * 4096 * 4 + 256
-    d3 = lib.make_desc(bank_params(3), "fp32")
+    d3 = lib.make_desc(bank_params("light_curve_share"), "fp32")
     assert lib.bank_bytes(d3) == 720000 * 2016 * 4 + 256   # L_pad = 2016 (multiple of 32)
-    d8 = lib.make_desc(bank_params(2), "fp8")
+    d8 = lib.make_desc(bank_params("strain"), "fp8")
     # one byte per tap, then an int32 exponent and a float template sum per template, then
     # the status word
     assert lib.bank_bytes(d8) == 65536 * 4096 + 65536 * 8 + 256
     # FFT form: a float32 complex spectrum of N/2 + 1 bins per template (rows of N/2 + 2),
     # N = 8192 for L = 4096
-    df = lib.make_desc(bank_params(2), "fft")
+    df = lib.make_desc(bank_params("strain"), "fft")
     assert lib.bank_bytes(df) == 65536 * (4096 + 2) * 8 + 256
     df.L = 4097
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(df)
     # F16F8: four bytes per tap (fp16 + two e4m3 codes), the FP8 side tables; L_pad = 2048
     # (multiple of 64) for L = 2000; L is capped by the strip's LDS footprint
-    dm = lib.make_desc(bank_params(3), "f16f8")
+    dm = lib.make_desc(bank_params("light_curve_share"), "f16f8")
     assert lib.bank_bytes(dm) == 720000 * 2048 * 4 + 720000 * 8 + 256
     dm.L = 4225
     with pytest.raises(lib.BflyError):
@@ -69,14 +69,14 @@ def test_bank_bytes_and_validation_on_host(lib):
     dm.L = 4224
     assert lib.bank_bytes(dm) == 720000 * 4224 * 4 + 720000 * 8 + 256
     # F16F6: fp16 (2 bytes) + two 6-bit codes per tap = 3.5 bytes, the same side tables
-    d6 = lib.make_desc(bank_params(3), "f16f6")
+    d6 = lib.make_desc(bank_params("light_curve_share"), "f16f6")
     assert lib.bank_bytes(d6) == 720000 * 2048 * 7 // 2 + 720000 * 8 + 256
     d6.L = 4225
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(d6)
     for bad in ({"L": 0}, {"L": 9000}, {"n_f0": 0}, {"fs": -1.0}, {"shard_index": 12},
                 {"f0_max": 1.0}, {"precision": 7}):
-        q = lib.make_desc(bank_params(2), "fp32")
+        q = lib.make_desc(bank_params("strain"), "fp32")
         for k, v in bad.items():
             setattr(q, k, v)
         with pytest.raises(lib.BflyError) as e:

@@ -12,7 +12,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import bfly_oracle as O  # noqa: E402
-from synth import bank_params, cfg4_batch  # noqa: E402
+from synth import bank_params, light_curve_batch  # noqa: E402
 from tests.parity_util import TOL, check_against_oracle, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -29,8 +29,8 @@ def bf():
 
 @pytest.mark.parametrize("prec", ["bf16x3"])
 def test_batched_light_curves_with_controls(bf, prec):
-    p = bank_params(4)
-    batch = cfg4_batch()
+    p = bank_params("light_curve_batch")
+    batch = light_curve_batch()
     series = sorted({e["series"] for e in batch},
                     key=lambda i: batch[2 * i]["x"].shape[0])[:6]
     picked = [e for e in batch if e["series"] in series]

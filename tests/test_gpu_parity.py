@@ -18,7 +18,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import bfly_oracle as O  # noqa: E402
-from synth import (BankParams, bank_params, cfg1_series, cfg2_series, cfg3_series,  # noqa: E402
+from synth import (BankParams, bank_params, small_strain_series, strain_series, light_curve_series,  # noqa: E402
                    chirp_samples, time_randomised, white_noise)
 from tests.parity_util import TOL, check_against_oracle, check_hist, to_np  # noqa: E402
 
@@ -53,8 +53,8 @@ def test_constant_offset(bf, prec, offset, norm):
     unit-variance strain-like series is raised or lowered far past its fluctuations.  Under
     the raw normalisation the level enters the normaliser and rho shrinks accordingly; the
     forms keep the raw frame there and are held to the same bound."""
-    p = bank_params(1)
-    x32 = (cfg1_series() + offset).astype(np.float32)
+    p = bank_params("small_strain")
+    x32 = (small_strain_series() + offset).astype(np.float32)
     x64 = x32.astype(np.float64)
     g, _ = _run(bf, p, x32, prec, norm=norm)
     orc = O.search(x64, p, norm=norm)
@@ -64,17 +64,17 @@ def test_constant_offset(bf, prec, offset, norm):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg1_full(bf, prec):
+def test_small_strain_full(bf, prec):
     """4 s at 512 Hz, bank 16x16, L = 512: every one of the 1537 offsets."""
-    p = bank_params(1)
-    x32 = cfg1_series().astype(np.float32)
+    p = bank_params("small_strain")
+    x32 = small_strain_series().astype(np.float32)
     x64 = x32.astype(np.float64)
     g, _ = _run(bf, p, x32, prec)
     orc = O.search(x64, p)
-    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"cfg1/{prec}")
-    check_hist(g, orc["m"], orc["degen"], TOL[prec], 256, 0.0, 1.0, f"cfg1/{prec}")
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"small_strain/{prec}")
+    check_hist(g, orc["m"], orc["degen"], TOL[prec], 256, 0.0, 1.0, f"small_strain/{prec}")
     assert np.allclose(g["spectrum"], orc["spectrum"], rtol=TOL[prec], atol=0)
-    print(f"cfg1 {prec}: {st}")
+    print(f"small_strain {prec}: {st}")
 
 
 def _edge_series(n, seed, L):
@@ -152,8 +152,8 @@ def test_batch_equals_single_bitwise(bf, prec):
 
 
 def test_determinism(bf):
-    p = bank_params(1)
-    x32 = cfg1_series().astype(np.float32)
+    p = bank_params("small_strain")
+    x32 = small_strain_series().astype(np.float32)
     a, _ = _run(bf, p, x32, "bf16x3")
     b, _ = _run(bf, p, x32, "bf16x3")
     for k in a:
@@ -164,7 +164,7 @@ def test_determinism(bf):
 def test_on_grid_recovery(bf, prec):
     """A bank template's chirp (amplitude 0.5) injected at sample 666 into unit noise is
     found at exactly that offset and template."""
-    p = bank_params(1)
+    p = bank_params("small_strain")
     gr = O.grid(p)
     k = 3 * 16 + 11
     for seed in (1, 2):
@@ -184,17 +184,17 @@ def _sample_offsets(W, centre, n_block, n_rand, seed):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg2_full_size_sampled(bf, prec):
+def test_strain_full_size_sampled(bf, prec):
     """32 s at 4096 Hz against 65,536 templates of L = 4096, at full size; the oracle checks
     a contiguous block around the injection plus random offsets and the two ends."""
-    p = bank_params(2)
-    x32 = cfg2_series()
+    p = bank_params("strain")
+    x32 = strain_series()
     x64 = x32.astype(np.float64)
     g, _ = _run(bf, p, x32, prec)
     W = x32.shape[0] - p.L + 1
     offs = _sample_offsets(W, 49152, 48, 80, seed=22)
     orc = O.search(x64, p, offsets=offs)
-    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"cfg2/{prec}")
+    st = check_against_oracle(x64, p, g, orc, TOL[prec], f"strain/{prec}")
     # properties at every offset
     assert np.array_equal(g["hist"], O.histogram(g["max_abs"].astype(np.float64),
                                                  g["argmax"] < 0, 256, 0.0, 1.0))
@@ -202,16 +202,16 @@ def test_cfg2_full_size_sampled(bf, prec):
     assert np.array_equal(spec.max(axis=1), g["max_abs"].astype(np.float64))
     assert np.allclose(g["spectrum"] * W, spec.sum(axis=0), rtol=1e-9, atol=0)
     assert np.all(g["max_abs"] <= 1.0 + 1e-5)
-    print(f"cfg2 {prec}: {st}")
+    print(f"strain {prec}: {st}")
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg3_share_with_control_sampled(bf, prec):
+def test_light_curve_share_with_control_sampled(bf, prec):
     """One GPU's 720,000-template share (L = 2000) against the 64 s light curve and its
     time-randomised control in one batch; oracle on sampled offsets of both."""
-    p = bank_params(3)
-    x = cfg3_series()
-    xc = cfg3_series(control=True)
+    p = bank_params("light_curve_share")
+    x = light_curve_series()
+    xc = light_curve_series(control=True)
     bank = bf.bank_create(p, prec)
     prm = bf.make_params()
     outs = bf.search_batch(bank, [torch.from_numpy(x).cuda(), torch.from_numpy(xc).cuda()], prm)
@@ -221,10 +221,10 @@ def test_cfg3_share_with_control_sampled(bf, prec):
     offs = [_sample_offsets(W, W // 2, 16, 24, seed=33), _sample_offsets(W, W // 3, 16, 24, 34)]
     orcs = O.search_many([x.astype(np.float64), xc.astype(np.float64)], p, offs)
     for gi, oi, xi, lab in zip(g, orcs, (x, xc), ("data", "control")):
-        st = check_against_oracle(xi.astype(np.float64), p, gi, oi, TOL[prec], f"cfg3/{lab}/{prec}")
+        st = check_against_oracle(xi.astype(np.float64), p, gi, oi, TOL[prec], f"light_curve/{lab}/{prec}")
         assert np.array_equal(gi["hist"], O.histogram(gi["max_abs"].astype(np.float64),
                                                       gi["argmax"] < 0, 256, 0.0, 1.0))
-        print(f"cfg3 {lab} {prec}: {st}")
+        print(f"light_curve {lab} {prec}: {st}")
     # the control keeps the value histogram of the data
     assert np.array_equal(np.sort(x), np.sort(xc))
 
@@ -246,9 +246,9 @@ def test_tile_shapes_bitwise_equal(bf, prec, shape, monkeypatch):
     got, _ = _run(bf, p, x32, prec, t_block=3, hist_bins=64)
     for k in ref:
         assert np.array_equal(ref[k].view(np.uint8), got[k].view(np.uint8)), (shape, k)
-    big = bank_params(1)
-    xb = cfg1_series().astype(np.float32)
+    big = bank_params("small_strain")
+    xb = small_strain_series().astype(np.float32)
     monkeypatch.setenv("BF_TILE", shape)
     g, _ = _run(bf, big, xb, prec)
     orc = O.search(xb.astype(np.float64), big)
-    check_against_oracle(xb.astype(np.float64), big, g, orc, TOL[prec], f"cfg1/{prec}/{shape}")
+    check_against_oracle(xb.astype(np.float64), big, g, orc, TOL[prec], f"small_strain/{prec}/{shape}")

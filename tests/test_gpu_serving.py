@@ -170,10 +170,10 @@ def test_serving_trace_segments_against_oracle(bf):
     sampled offsets of the two shortest injected and two shortest plain segments match the
     FP64 oracle, and a strong injected chirp's offset carries a larger maximum than the noise
     around it."""
-    from synth import bank_params, cfg5_segment, cfg5_trace
+    from synth import bank_params, serving_segment, serving_trace
     from tests.parity_util import check_against_oracle
-    p = bank_params(5)
-    trace = cfg5_trace(64)
+    p = bank_params("serving")
+    trace = serving_trace(64)
     inj = sorted([e for e in trace if e["inject"]], key=lambda e: e["n"])[:2]
     plain = sorted([e for e in trace if not e["inject"]], key=lambda e: e["n"])[:2]
     picked = inj + plain
@@ -181,7 +181,7 @@ def test_serving_trace_segments_against_oracle(bf):
     prm = bf.make_params(t_block=256)
     srv = bf.server_create(bank, hbm_budget_bytes=8 << 30, max_slots=8, ticks_in_flight=2,
                            params=prm)
-    xs = [cfg5_segment(e) for e in picked]
+    xs = [serving_segment(e) for e in picked]
     tickets = [bf.submit(srv, x) for x in xs]
     _wait(bf, srv, tickets, timeout=300.0)
     outs = [bf.fetch(srv, t, x.shape[0]) for t, x in zip(tickets, xs)]

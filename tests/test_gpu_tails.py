@@ -16,7 +16,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import bfly_oracle as O  # noqa: E402
-from synth import BankParams, bank_params, cfg1_series, time_randomised, white_noise  # noqa: E402
+from synth import BankParams, bank_params, small_strain_series, time_randomised, white_noise  # noqa: E402
 from tests.parity_util import TOL, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -121,14 +121,14 @@ def test_tails_small_with_edges(bf, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fft"])
-def test_tails_cfg1(bf, prec):
+def test_tails_small_strain(bf, prec):
     """4 s at 512 Hz with a chirp, bank 16 x 16, L = 512, kappa = 4: every offset."""
-    p = bank_params(1)
-    x32 = cfg1_series().astype(np.float32)
+    p = bank_params("small_strain")
+    x32 = small_strain_series().astype(np.float32)
     bank = bf.bank_create(p, prec)
     _, tails = _search_tails(bf, bank, [x32], 4.0, 1 << 18)
     orc = O.sigma_tails(x32.astype(np.float64), p, 4.0)
-    st = check_tails(x32.astype(np.float64), p, tails[0], orc, 4.0, TOL[prec], f"cfg1/{prec}")
+    st = check_tails(x32.astype(np.float64), p, tails[0], orc, 4.0, TOL[prec], f"small_strain/{prec}")
     print(prec, st)
     assert st["n_fp64"] > 0
 
