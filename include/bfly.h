@@ -177,6 +177,20 @@ bf_status bf_search_batch(const bf_bank* bank, const bf_segment* segs, int32_t n
                           const bf_search_params* params, void* workspace,
                           size_t workspace_bytes, bf_stream stream);
 
+/* The search of bf_search_segment for callers that cannot allocate memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results, bit for bit, with the workspace taken from a device array of 32 MiB built
+ * into the library (one per GPU, held until the process ends) and the batch table written
+ * by a kernel from its arguments.  No host or device memory is allocated by the call.
+ * Limit: table + bf_workspace_bytes of the series <= 32 MiB (about 540,000 samples at
+ * L = 4096 for the direct forms); a larger series returns BF_EINVAL.  The array keeps the
+ * last call's contents and is cleared by the search itself where it must start at zero.
+ * Calls that overlap on one GPU (two streams, two threads) share the array and race: the
+ * caller serialises them.  Timing records (bf_set_timing) are not taken. */
+bf_status bf_search_segment_noalloc(const bf_bank* bank, const float* x, int64_t n,
+                                    const bf_search_params* params, const bf_result* out,
+                                    bf_stream stream);
+
 /* ---- kappa-sigma tails (Sec. 2.2 and the Fig. 5 caption: only correlations above kappa
  * sigma leave the GPU; Fig. 6 caption: pseudo-spectra of their counts) -------------------
  * sigma_k of a series = sqrt(mean over its non-degenerate offsets of rho_k(tau)^2): the

@@ -26,8 +26,13 @@ Everything is float64.  The correlation numerator is a plain matrix product of t
 matrix with the window (Hankel) matrix; the window energy is a two-pass centred sum per
 window (no prefix sums), so it is independent of how the GPU computes it.
 
-Parity status: every function here is pinned by the CPU tests (brute force, library
-routines, closed forms, invariants); none is "parity unpinned".
+Parity status: every function is pinned by the CPU tests (tests/pins.py), none is "parity
+unpinned": templates by hand-derived closed forms and mean/norm identities; the numerator by
+numpy.correlate, scipy's FFT correlation and its own FFT path; search and search_many (one
+core: several series, chunks of the bank, sharded banks, the runner-up |rho|) by pure-Python
+brute force and invariants; rho_at by brute force at given pairs; sigma and the tails by
+brute force and Parseval's theorem; the coincidence by pairwise loops.  Planted mistakes in
+each (tests/test_oracle_mutants.py) fail at least one pin.
 """
 
 from __future__ import annotations
@@ -201,63 +206,96 @@ def decimate(S: np.ndarray, t_block: int) -> np.ndarray:
 def search(x: np.ndarray, p, offsets: np.ndarray | None = None, norm: str = "centred",
            hist_bins: int = 256, hist_lo: float = 0.0, hist_hi: float = 1.0,
            k_chunk: int | None = None) -> dict:
-    """The whole search on the offsets given (all W offsets when ``offsets`` is None).
+    """The whole search of one series on the offsets given (all W offsets when ``offsets``
+    is None); ``search_many`` with a single series.
 
     Returns a dict with
       m[T]        max_k |rho(tau, k)|           (butterfly output; 0 on degenerate windows)
       a[T]        the smallest global k reaching m (reading 12); -1 on degenerate windows
+      second[T]   the second largest |rho(tau, k)| over the bank (equal to m when two
+                  templates tie for the maximum; -1 for a one-template bank; 0 on degenerate
+                  windows): m - second is the top-2 margin that decides where an argmax is
+                  unique at a given tolerance (reading 22)
       S[T, B]     max over the fdot templates of f0 bin i of |rho|  (chirp spectrogram)
       degen[T]    degenerate-window flags
       hist[B_h]   histogram of m over non-degenerate offsets
       n_degenerate
       spectrum[B] time mean of S over the offsets given (over all W: the broadband spectrum)
       offsets[T]
-    Templates are generated and applied in chunks of whole f0 bins to bound memory; the
-    reductions merge chunks in increasing k with strict comparisons, so ties keep the
-    smallest k.
     """
-    x = np.asarray(x, dtype=np.float64)
+    return search_many([x], p, [offsets], norm, hist_bins, hist_lo, hist_hi, k_chunk)[0]
+
+
+def search_many(xs: list, p, offsets_list: list | None = None, norm: str = "centred",
+                hist_bins: int = 256, hist_lo: float = 0.0, hist_hi: float = 1.0,
+                k_chunk: int | None = None) -> list:
+    """``search`` for several series (each on its own offsets, None = all), generating each
+    template chunk once for all of them.  Returns one dict per series, as ``search``.
+
+    Templates are generated and applied in chunks of whole f0 bins (``k_chunk`` templates,
+    rounded down to whole bins; by default sized to bound memory); the reductions merge the
+    chunks in increasing k with strict comparisons, so ties keep the smallest k."""
     g = grid(p)
     L = p.L
-    W = x.shape[0] - L + 1
-    if W < 1:
-        raise ValueError("series shorter than the template")
-    offs = np.arange(W) if offsets is None else np.asarray(offsets, dtype=np.int64)
-    T = offs.shape[0]
-    E, _, degen = window_energy(x, L, offs, norm)
-    Xw = windows(x, L, offs)
-    Xw = np.where(np.isfinite(Xw), Xw, 0.0)
-    scale = np.zeros(T)
-    scale[~degen] = 1.0 / np.sqrt(E[~degen])
-
     nb, nfd = g.n_bins, g.n_fdot
+    if offsets_list is None:
+        offsets_list = [None] * len(xs)
+    series = []
+    for x, offs in zip(xs, offsets_list):
+        x = np.asarray(x, dtype=np.float64)
+        W = x.shape[0] - L + 1
+        if W < 1:
+            raise ValueError("series shorter than the template")
+        offs = np.arange(W) if offs is None else np.asarray(offs, dtype=np.int64)
+        T = offs.shape[0]
+        E, _, degen = window_energy(x, L, offs, norm)
+        Xw = windows(x, L, offs)
+        Xw = np.where(np.isfinite(Xw), Xw, 0.0)
+        scale = np.zeros(T)
+        scale[~degen] = 1.0 / np.sqrt(E[~degen])
+        series.append({"Xw": Xw, "scale": scale, "degen": degen, "offsets": offs,
+                       "m": np.full(T, -1.0), "second": np.full(T, -1.0),
+                       "a": np.full(T, -1, dtype=np.int64), "S": np.zeros((T, nb))})
+
+    T_all = sum(q["offsets"].shape[0] for q in series)
     if k_chunk is None:
-        k_chunk = max(nfd, (1 << 22) // max(T, 1) // nfd * nfd)
+        k_chunk = max(nfd, (1 << 22) // max(T_all, 1) // nfd * nfd)
     bins_per_chunk = max(1, k_chunk // nfd)
-    m = np.full(T, -1.0)
-    a = np.full(T, -1, dtype=np.int64)
-    S = np.zeros((T, nb))
     for b0 in range(0, nb, bins_per_chunk):
         b1 = min(nb, b0 + bins_per_chunk)
         k0, k1 = b0 * nfd, b1 * nfd
         H = templates(p.fs, L, g.f0[k0:k1], g.fdot[k0:k1])
-        r = np.abs((Xw @ H.T) * scale[:, None])          # |rho| [T, k1-k0]
-        S[:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)
-        j = np.argmax(r, axis=1)                          # first maximum in this chunk
-        v = r[np.arange(T), j]
-        better = v > m
-        m[better] = v[better]
-        a[better] = g.k_global[k0 + j[better]]
-    m[degen] = 0.0
-    a[degen] = -1
-    S[degen] = 0.0
-    return {
-        "m": m, "a": a, "S": S, "degen": degen,
-        "hist": histogram(m, degen, hist_bins, hist_lo, hist_hi),
-        "n_degenerate": int(degen.sum()),
-        "spectrum": S.mean(axis=0),
-        "offsets": offs,
-    }
+        for q in series:
+            T = q["offsets"].shape[0]
+            r = np.abs((q["Xw"] @ H.T) * q["scale"][:, None])          # |rho|
+            q["S"][:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)
+            j = np.argmax(r, axis=1)                          # first maximum in this chunk
+            v = r[np.arange(T), j]
+            # the chunk's second largest value (ties count twice)
+            c2 = np.partition(r, -2, axis=1)[:, -2] if k1 - k0 > 1 else np.full(T, -1.0)
+            # top two of {m, second, v, c2}: the larger maximum, and the larger of the
+            # smaller maximum and both runners-up
+            q["second"] = np.maximum(np.minimum(q["m"], v), np.maximum(q["second"], c2))
+            better = v > q["m"]
+            q["m"][better] = v[better]
+            q["a"][better] = g.k_global[k0 + j[better]]
+
+    out = []
+    for q in series:
+        degen = q["degen"]
+        m, a, S, second = q["m"], q["a"], q["S"], q["second"]
+        m[degen] = 0.0
+        a[degen] = -1
+        S[degen] = 0.0
+        second[degen] = 0.0
+        out.append({
+            "m": m, "a": a, "second": second, "S": S, "degen": degen,
+            "hist": histogram(m, degen, hist_bins, hist_lo, hist_hi),
+            "n_degenerate": int(degen.sum()),
+            "spectrum": S.mean(axis=0),
+            "offsets": q["offsets"],
+        })
+    return out
 
 
 def average_spectrum(spectra: list[np.ndarray]) -> np.ndarray:
@@ -266,36 +304,11 @@ def average_spectrum(spectra: list[np.ndarray]) -> np.ndarray:
     return np.mean(np.stack(spectra), axis=0)
 
 
-def top2_margin(x: np.ndarray, p, offsets: np.ndarray, norm: str = "centred") -> np.ndarray:
-    """For each offset, max |rho| minus the second-largest |rho| over the bank.  Used to
-    decide where an argmax comparison is meaningful at a given tolerance."""
-    x = np.asarray(x, dtype=np.float64)
-    g = grid(p)
-    offs = np.asarray(offsets, dtype=np.int64)
-    E, _, degen = window_energy(x, p.L, offs, norm)
-    Xw = np.where(np.isfinite(windows(x, p.L, offs)), windows(x, p.L, offs), 0.0)
-    scale = np.zeros(offs.shape[0])
-    scale[~degen] = 1.0 / np.sqrt(E[~degen])
-    best = np.full(offs.shape[0], -1.0)
-    second = np.full(offs.shape[0], -1.0)
-    nfd = g.n_fdot
-    step = max(nfd, (1 << 22) // max(offs.shape[0], 1) // nfd * nfd)
-    K = g.f0.shape[0]
-    for k0 in range(0, K, step):
-        k1 = min(K, k0 + step)
-        H = templates(p.fs, p.L, g.f0[k0:k1], g.fdot[k0:k1])
-        r = np.abs((Xw @ H.T) * scale[:, None])
-        part = -np.sort(-r, axis=1)[:, :2]
-        cand = np.concatenate([best[:, None], second[:, None], part], axis=1)
-        cand = -np.sort(-cand, axis=1)
-        best, second = cand[:, 0], cand[:, 1]
-    return best - second
-
-
 def rho_at(x: np.ndarray, p, offsets: np.ndarray, k_global: np.ndarray,
            norm: str = "centred") -> np.ndarray:
     """|rho(tau_i, k_i)| in float64 for given (offset, global template index) pairs; used to
-    check that a reported argmax really reaches the reported maximum.  k_i = -1 gives 0."""
+    check that a reported argmax really reaches the reported maximum.  k_i = -1 gives 0, as
+    does a degenerate window."""
     x = np.asarray(x, dtype=np.float64)
     g = grid(p)
     offs = np.asarray(offsets, dtype=np.int64)
@@ -315,49 +328,6 @@ def rho_at(x: np.ndarray, p, offsets: np.ndarray, k_global: np.ndarray,
     r = np.zeros(d.shape[0])
     r[~degen] = np.abs(d[~degen]) / np.sqrt(E[~degen])
     out[ok] = r
-    return out
-
-
-def search_many(xs: list, p, offsets_list: list, norm: str = "centred") -> list:
-    """``search`` for several series at once (each on its own offsets), generating every
-    template chunk once.  Returns one dict per series with m, a, S, degen, offsets."""
-    g = grid(p)
-    L = p.L
-    nb, nfd = g.n_bins, g.n_fdot
-    prep = []
-    for x, offs in zip(xs, offsets_list):
-        x = np.asarray(x, dtype=np.float64)
-        offs = np.asarray(offs, dtype=np.int64)
-        E, _, degen = window_energy(x, L, offs, norm)
-        Xw = np.where(np.isfinite(windows(x, L, offs)), windows(x, L, offs), 0.0)
-        scale = np.zeros(offs.shape[0])
-        scale[~degen] = 1.0 / np.sqrt(E[~degen])
-        T = offs.shape[0]
-        prep.append({"Xw": Xw, "scale": scale, "degen": degen, "offsets": offs,
-                     "m": np.full(T, -1.0), "a": np.full(T, -1, dtype=np.int64),
-                     "S": np.zeros((T, nb))})
-    T_all = sum(q["offsets"].shape[0] for q in prep)
-    bins_per_chunk = max(1, (1 << 22) // max(T_all, 1) // nfd)
-    for b0 in range(0, nb, bins_per_chunk):
-        b1 = min(nb, b0 + bins_per_chunk)
-        k0, k1 = b0 * nfd, b1 * nfd
-        H = templates(p.fs, L, g.f0[k0:k1], g.fdot[k0:k1])
-        for q in prep:
-            T = q["offsets"].shape[0]
-            r = np.abs((q["Xw"] @ H.T) * q["scale"][:, None])
-            q["S"][:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)
-            j = np.argmax(r, axis=1)
-            v = r[np.arange(T), j]
-            better = v > q["m"]
-            q["m"][better] = v[better]
-            q["a"][better] = g.k_global[k0 + j[better]]
-    out = []
-    for q in prep:
-        d = q["degen"]
-        q["m"][d] = 0.0
-        q["a"][d] = -1
-        q["S"][d] = 0.0
-        out.append({"m": q["m"], "a": q["a"], "S": q["S"], "degen": d, "offsets": q["offsets"]})
     return out
 
 

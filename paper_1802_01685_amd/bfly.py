@@ -29,7 +29,7 @@ EXPORTED = ["bf_bank_bytes", "bf_bank_create", "bf_bank_info", "bf_bank_destroy"
             "bf_server_create", "bf_server_request_bytes", "bf_submit", "bf_poll", "bf_fetch",
             "bf_cancel", "bf_server_stats", "bf_server_destroy",
             "bf_tails_workspace_bytes", "bf_search_tails",
-            "bf_coincidence_workspace_bytes", "bf_coincidence"]
+            "bf_coincidence_workspace_bytes", "bf_coincidence", "bf_search_segment_noalloc"]
 STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
                               vp, sz, vp],
         "bf_search_batch": [vp, ctypes.POINTER(Segment), i32, ctypes.POINTER(SearchParams), vp,
                             sz, vp],
+        "bf_search_segment_noalloc": [vp, vp, i64, ctypes.POINTER(SearchParams),
+                                      ctypes.POINTER(Result), vp],
         "bf_plan": [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "bf_set_timing": [i32],
         "bf_kernel_times": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
@@ -154,6 +156,22 @@ def _stream(stream) -> int:
 
 def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
+
+
+def _record_on(stream, tensors) -> None:
+    """When the work runs on a stream other than torch's current one, tell the caching
+    allocator that the tensors this binding allocated are in use on that stream: otherwise a
+    tensor dropped at return could be handed to the next allocation on the current stream
+    while the kernels still read or write it."""
+    if stream is None:
+        return
+    ts = stream if isinstance(stream, torch.cuda.Stream) else \
+        torch.cuda.ExternalStream(_stream(stream))
+    if ts.cuda_stream == torch.cuda.current_stream().cuda_stream:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(ts)
 
 
 def make_desc(p, precision: str = "fp32") -> BankDesc:
@@ -266,13 +284,34 @@ def search_segment(bank: Bank, x: torch.Tensor, params: SearchParams | None = No
     params = params or make_params()
     assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
     n = x.shape[0]
+    own = [] if out is not None else None
     out = out if out is not None else alloc_outputs(bank, n, params, x.device)
+    if own is None:
+        own = list(out.values())
     ws = workspace if workspace is not None else alloc_workspace(bank, [n], params, x.device)
+    if workspace is None:
+        own.append(ws)
     res = _result(out)
     _check(lib().bf_search_segment(ctypes.c_void_p(bank.handle), ctypes.c_void_p(x.data_ptr()),
                                    n, ctypes.byref(params), ctypes.byref(res),
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    ctypes.c_void_p(_stream(stream))))
+    _record_on(stream, own)
+    return out
+
+
+def search_segment_noalloc(bank: Bank, x: torch.Tensor, out: dict,
+                           params: SearchParams | None = None, stream=None) -> dict:
+    """bf_search_segment_noalloc: the search of search_segment with the library's own
+    device scratch array as workspace (no allocation in the call).  The caller passes the
+    output tensors (alloc_outputs); calls on one GPU must not overlap."""
+    params = params or make_params()
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    res = _result(out)
+    _check(lib().bf_search_segment_noalloc(ctypes.c_void_p(bank.handle),
+                                           ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                           ctypes.byref(params), ctypes.byref(res),
+                                           ctypes.c_void_p(_stream(stream))))
     return out
 
 
@@ -284,9 +323,13 @@ def search_batch(bank: Bank, xs: list, params: SearchParams | None = None,
     ns = [int(x.shape[0]) for x in xs]
     for x in xs:
         assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
-    outs = outs if outs is not None else [alloc_outputs(bank, n, params, x.device)
-                                          for n, x in zip(ns, xs)]
+    own = []
+    if outs is None:
+        outs = [alloc_outputs(bank, n, params, x.device) for n, x in zip(ns, xs)]
+        own += [t for o in outs for t in o.values()]
     ws = workspace if workspace is not None else alloc_workspace(bank, ns, params, xs[0].device)
+    if workspace is None:
+        own.append(ws)
     segs = (Segment * len(xs))()
     for i, (x, o) in enumerate(zip(xs, outs)):
         segs[i].x = x.data_ptr()
@@ -295,6 +338,7 @@ def search_batch(bank: Bank, xs: list, params: SearchParams | None = None,
     _check(lib().bf_search_batch(ctypes.c_void_p(bank.handle), segs, len(xs),
                                  ctypes.byref(params), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), ctypes.c_void_p(_stream(stream))))
+    _record_on(stream, own)
     return outs
 
 
@@ -328,11 +372,17 @@ def search_tails(bank: Bank, xs: list, kappa: float, capacity: int,
     ns = [int(x.shape[0]) for x in xs]
     for x in xs:
         assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
-    outs = outs if outs is not None else [alloc_outputs(bank, n, params, x.device)
-                                          for n, x in zip(ns, xs)]
-    tails = tails if tails is not None else [alloc_tails(bank, capacity, x.device) for x in xs]
+    own = []
+    if outs is None:
+        outs = [alloc_outputs(bank, n, params, x.device) for n, x in zip(ns, xs)]
+        own += [t for o in outs for t in o.values()]
+    if tails is None:
+        tails = [alloc_tails(bank, capacity, x.device) for x in xs]
+        own += [t for o in tails for t in o.values()]
     ws = workspace if workspace is not None else torch.empty(
         tails_workspace_bytes(bank, ns, params), dtype=torch.uint8, device=xs[0].device)
+    if workspace is None:
+        own.append(ws)
     segs = (TailSegment * len(xs))()
     for i, (x, o, t) in enumerate(zip(xs, outs, tails)):
         segs[i].x = x.data_ptr()
@@ -345,6 +395,7 @@ def search_tails(bank: Bank, xs: list, kappa: float, capacity: int,
                                  ctypes.c_float(kappa), ctypes.byref(params),
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  ctypes.c_void_p(_stream(stream))))
+    _record_on(stream, own)
     return outs, tails
 
 
@@ -375,7 +426,7 @@ def coincidence(bank: Bank, tails_a: dict, tails_b: dict, n_offsets: int, dtau: 
                                 ctypes.c_void_p(out["n_pairs"].data_ptr()),
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                 ctypes.c_void_p(_stream(stream))))
-    out["_workspace"] = ws    # keep alive until the stream has run
+    _record_on(stream, [ws] + list(out.values()))
     return out
 
 

@@ -14,6 +14,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -22,7 +23,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfly.so")
 
 ARCH = "gfx950"
-SOURCES = ["bfly_kernels.hip", "bfly_fft.hip", "bfly_coinc.hip", "bfly_api.cpp", "bfly_server.cpp"]
+SOURCES = ["bfly_kernels.hip", "bfly_fft.hip", "bfly_coinc.hip", "bfly_noalloc.hip", "bfly_api.cpp",
+           "bfly_server.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     "-ffp-contract=off",
@@ -51,11 +53,14 @@ def _run(cmd: list[str]) -> None:
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     with tempfile.TemporaryDirectory(prefix="bfly_build_") as tmp:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj])
-            objs.append(obj)
+        objs = [os.path.join(tmp, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or
+                          (os.cpu_count() or 1)))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_run, c) for c in cmds]:
+                f.result()
         tmp_lib = os.path.join(tmp, "libbfly.so")
         _run([hipcc, *DEVICE, "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp_lib])
         shutil.copyfile(tmp_lib, LIB + ".tmp")

@@ -245,11 +245,16 @@ struct TimingLog {
 };
 thread_local TimingLog t_timing;
 
+}  // namespace
+
+namespace bfly {
+
 // tails: per-series tail outputs for a tail search (else null), with its kappa.
+// upload: how the batch table reaches the workspace (see TableUpload).
 bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
                     const bf_search_params* prm, void* workspace, size_t ws_bytes,
-                    hipStream_t stream, const bf_tails* tails = nullptr,
-                    float kappa = 0.0f) {
+                    hipStream_t stream, const bf_tails* tails, float kappa,
+                    TableUpload upload) {
   if (!bank) return fail(BF_EINVAL, "bank is NULL");
   if (!segs || n_segs < 1) return fail(BF_EINVAL, "need at least one series");
   bf_status st = check_params(prm);
@@ -272,7 +277,11 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   if (ws_bytes < need)
     return fail(BF_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   if (((uintptr_t)workspace & 255) != 0) return fail(BF_EINVAL, "workspace not 256-byte aligned");
-  if ((st = check_device_ptr(workspace, "workspace")) != BF_OK) return st;
+  if (upload == TableUpload::Kernel && n_segs != 1)
+    return fail(BF_EINVAL, "the kernel-written table holds one series");
+  if (upload == TableUpload::Staging &&
+      (st = check_device_ptr(workspace, "workspace")) != BF_OK)
+    return st;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
   if (dev != bank->device)
@@ -299,11 +308,14 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   // the FFT form's search pass is a plain search; its sigma pass comes after
   const SearchDev sp = make_search(b, prm, with_tails && b.precision != P_FFT ? MODE_SIGMA
                                                                            : MODE_SEARCH, kappa);
-  std::vector<SeriesBufs> sb((size_t)n_segs);
+  SeriesBufs one;                 // a single series needs no host allocation
+  std::vector<SeriesBufs> many;
+  if (n_segs > 1) many.resize((size_t)n_segs);
+  SeriesBufs* sb = n_segs > 1 ? many.data() : &one;
   char* ws = (char*)workspace;
   size_t off = table_bytes(n_segs);
   for (int32_t i = 0; i < n_segs; ++i) {
-    SeriesBufs& q = sb[(size_t)i];
+    SeriesBufs& q = sb[i];
     series_ws_carve(b, segs[i].n, ws + off, &q, with_tails);
     off += series_ws_bytes(b, segs[i].n, with_tails);
     q.x = segs[i].x;
@@ -314,23 +326,33 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   int slots = 0;
   if ((st = device_slots(&slots)) != BF_OK) return st;
 
-  Staging* stg = acquire_staging(table_bytes(n_segs), dev, &st);
-  if (!stg) return st;
-  BatchHdr* hdr = (BatchHdr*)stg->host;
-  const TableInfo ti = fill_table(b, sp, sb.data(), n_segs, slots, hdr);
   BatchHdr* tab_dev = (BatchHdr*)ws;
-  hipError_t e = hipMemcpyAsync(tab_dev, hdr, table_bytes(n_segs), hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) {
-    release_staging(stg, false);
-    return hip_fail(e, "hipMemcpyAsync(series table)");
+  TableInfo ti;
+  if (upload == TableUpload::Kernel) {
+    OneSeriesTable tab;
+    ti = fill_table(b, sp, sb, 1, slots, &tab.hdr);
+    HIP_TRY(launch_put_table(tab, (OneSeriesTable*)tab_dev, stream), "k_put_table launch");
+  } else {
+    Staging* stg = acquire_staging(table_bytes(n_segs), dev, &st);
+    if (!stg) return st;
+    BatchHdr* hdr = (BatchHdr*)stg->host;
+    ti = fill_table(b, sp, sb, n_segs, slots, hdr);
+    hipError_t e =
+        hipMemcpyAsync(tab_dev, hdr, table_bytes(n_segs), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+      release_staging(stg, false);
+      return hip_fail(e, "hipMemcpyAsync(series table)");
+    }
+    e = hipEventRecord(stg->ev, stream);
+    release_staging(stg, e == hipSuccess);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   }
-  e = hipEventRecord(stg->ev, stream);
-  release_staging(stg, e == hipSuccess);
-  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
 
   if (b.precision != P_FFT) HIP_TRY(prepare_main(b, sp), "hipFuncSetAttribute(k_main)");
+  // the kernel-written table is the no-allocation path: no timing records (they create events)
   TimingSet* te = nullptr;
-  if (g_timing && (te = timing_slot(dev, &st)) == nullptr) return st;
+  if (g_timing && upload == TableUpload::Staging && (te = timing_slot(dev, &st)) == nullptr)
+    return st;
   const int32_t xb =
       (int32_t)std::min<int64_t>(std::max<int64_t>((ti.max_words + 255) / 256, 1), 2048);
   if (!with_tails) return enqueue_kernels(b, sp, tab_dev, n_segs, xb, ti.n_items, stream, te);
@@ -339,10 +361,6 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   if (b.precision != P_FFT) HIP_TRY(prepare_main(b, sp_t), "hipFuncSetAttribute(k_main)");
   return enqueue_tail_kernels(b, sp, sp_t, tab_dev, n_segs, xb, ti.n_items, stream, te);
 }
-
-}  // namespace
-
-namespace bfly {
 
 size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails) {
   const int64_t W = n - b.L + 1;
@@ -599,9 +617,6 @@ bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
 
 }  // namespace bfly
 
-namespace {
-}  // namespace
-
 // =======================================================================================
 extern "C" {
 
@@ -715,7 +730,8 @@ bf_status bf_search_segment(const bf_bank* bank, const float* x, int64_t n,
     s.x = x;
     s.n = n;
     s.out = *out;
-    return run_batch(bank, &s, 1, params, workspace, workspace_bytes, (hipStream_t)stream);
+    return run_batch(bank, &s, 1, params, workspace, workspace_bytes, (hipStream_t)stream,
+                     nullptr, 0.0f, TableUpload::Staging);
   } catch (...) {
     return fail(BF_ENOMEM, "internal error");
   }
@@ -726,7 +742,7 @@ bf_status bf_search_batch(const bf_bank* bank, const bf_segment* segs, int32_t n
                           size_t workspace_bytes, bf_stream stream) {
   try {
     return run_batch(bank, segs, n_segs, params, workspace, workspace_bytes,
-                     (hipStream_t)stream);
+                     (hipStream_t)stream, nullptr, 0.0f, TableUpload::Staging);
   } catch (...) {
     return fail(BF_ENOMEM, "internal error");
   }
@@ -767,7 +783,7 @@ bf_status bf_search_tails(const bf_bank* bank, const bf_tail_segment* segs, int3
       tt[(size_t)i] = segs[i].tails;
     }
     return run_batch(bank, ss.data(), n_segs, params, workspace, workspace_bytes,
-                     (hipStream_t)stream, tt.data(), kappa);
+                     (hipStream_t)stream, tt.data(), kappa, TableUpload::Staging);
   } catch (...) {
     return fail(BF_ENOMEM, "internal error");
   }

@@ -28,8 +28,9 @@ namespace {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex product with fused multiply-adds: each component rounds once after one product.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -59,6 +60,52 @@ constexpr int bitrev(int i, int R) {
   return r;
 }
 
+// b * exp(-+2 pi i q / 16) for a compile-time q in 0..7: a quarter turn is a swap and a sign,
+// an eighth turn two products by sqrt(1/2), the rest one complex product.
+template <int Q, bool INV>
+__device__ __forceinline__ float2 twiddle16(float2 b) {
+  constexpr float R2 = 0.70710678118654752f;
+  if constexpr (Q == 0) {
+    return b;
+  } else if constexpr (Q == 4) {
+    return INV ? make_float2(-b.y, b.x) : make_float2(b.y, -b.x);
+  } else if constexpr (Q == 2) {
+    return INV ? make_float2((b.x - b.y) * R2, (b.x + b.y) * R2)
+               : make_float2((b.x + b.y) * R2, (b.y - b.x) * R2);
+  } else if constexpr (Q == 6) {
+    return INV ? make_float2(-(b.x + b.y) * R2, (b.x - b.y) * R2)
+               : make_float2((b.y - b.x) * R2, -(b.x + b.y) * R2);
+  } else {
+    return cmul(b, make_float2(C16[Q], INV ? S16[Q] : -S16[Q]));
+  }
+}
+
+// One radix-2 stage of span S (s in the DIT recursion) over t[], groups of S from offset G.
+template <int R, int S, int G, int K, bool INV>
+__device__ __forceinline__ void dft_bfly(float2 (&t)[R]) {
+  if constexpr (K < S / 2) {
+    const float2 a = t[G + K];
+    const float2 b = twiddle16<K * (16 / S), INV>(t[G + K + S / 2]);
+    t[G + K] = cadd(a, b);
+    t[G + K + S / 2] = csub(a, b);
+    dft_bfly<R, S, G, K + 1, INV>(t);
+  }
+}
+template <int R, int S, int G, bool INV>
+__device__ __forceinline__ void dft_stage(float2 (&t)[R]) {
+  if constexpr (G < R) {
+    dft_bfly<R, S, G, 0, INV>(t);
+    dft_stage<R, S, G + S, INV>(t);
+  }
+}
+template <int R, int S, bool INV>
+__device__ __forceinline__ void dft_stages(float2 (&t)[R]) {
+  if constexpr (S <= R) {
+    dft_stage<R, S, 0, INV>(t);
+    dft_stages<R, 2 * S, INV>(t);
+  }
+}
+
 // In-register DFT of size R (2, 4, 8 or 16), natural order in and out: radix-2
 // decimation in time after a bit-reversal permutation.
 template <int R, bool INV>
@@ -66,21 +113,7 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   float2 t[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) t[bitrev(i, R)] = v[i];
-#pragma unroll
-  for (int s = 2; s <= R; s <<= 1) {
-    const int h = s / 2;
-#pragma unroll
-    for (int g = 0; g < R; g += s)
-#pragma unroll
-      for (int k = 0; k < h; ++k) {
-        const int q = k * (16 / s);
-        const float2 w = make_float2(C16[q], INV ? S16[q] : -S16[q]);
-        const float2 a = t[g + k];
-        const float2 b = q == 0 ? t[g + k + h] : cmul(t[g + k + h], w);
-        t[g + k] = cadd(a, b);
-        t[g + k + h] = csub(a, b);
-      }
-  }
+  dft_stages<R, 2, INV>(t);
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
@@ -270,7 +303,7 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_bank(GridDev g, BankDev b,
 // Data spectra: one work-group per (series, block) tile, persistent over the batch's tiles.
 template <int M>
 __global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restrict__ hdr,
-                                                          BankDev b, int norm) {
+                                                          BankDev b) {
   constexpr int T = Plan<M>::T;
   __shared__ float2 buf[Padded<M>::n];
   const SegDesc* segs = hdr_segs(hdr);
@@ -286,7 +319,7 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restr
     const int64_t tau0 = (tt - sg.tile0) * valid;
     // x - c0 (see series_offset); padding past the end and non-finite samples stage as 0, so
     // a constant level does not enter the block's norm and with it the transform's rounding
-    const float c0 = series_offset(sg, norm);
+    const float c0 = series_offset(sg);
     auto xs = [&](int64_t gi) -> float {
       if (gi >= sg.n) return 0.0f;
       const float v = sg.x[gi];
@@ -369,7 +402,9 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
   const int64_t n_items = hdr->n_items;
   const int valid = 2 * M - b.L + 1;
   const int tid = threadIdx.x;
-  const float scale = 1.0f / (float)M;
+  // 1/M of the inverse transform, times the 1/2 of the even/odd split (applied to the
+  // outputs: both are powers of two, so moving them changes no rounding)
+  const float scale = 0.5f / (float)M;
   const int nfd = b.n_fdot;
 
   // per-thread constants: the post-processing twiddle exp(+2 pi i p / N) of pair
@@ -436,8 +471,9 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
           const int p2 = M - pp;
           const float2 c1 = cmul(cconj(h1[q]), xs[pp]);
           const float2 c2 = cmul(cconj(h2[q]), xs[p2]);
-          const float2 e = cscale(cadd(c1, cconj(c2)), 0.5f);
-          const float2 d = cscale(csub(c1, cconj(c2)), 0.5f);
+          // twice E and O (the 1/2 is in `scale`)
+          const float2 e = cadd(c1, cconj(c2));
+          const float2 d = csub(c1, cconj(c2));
           const float2 w = q == 0 ? wb : cmul(wb, make_float2(C16[q], S16[q]));
           const float2 o = cmul(d, w);
           buf[pad(pp)] = make_float2(e.x - o.y, e.y + o.x);                 // E + iO
@@ -552,7 +588,7 @@ hipError_t launch_fft_bank_t(const GridDev& g, const BankDev& b, void* dst, unsi
 template <int M>
 hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                                const SearchDev& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b, p.norm);
+  hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (fft_occupancy() == 4)

@@ -25,8 +25,16 @@ constexpr int MAX_FFT_L = 4096;              // FFT form: N = 2M <= 8192
 constexpr int MAX_F16F8_L = 4224;            // F16F8, F16F6: 24-byte strip cells + 36 KB
                                              // fill 160 KB LDS
 constexpr int MAX_HIST_BINS = 4096;
-constexpr double SPEC_FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point spectrum sums
-constexpr double SIGMA_FIX_SCALE = 68719476736.0;   // 2^36: fixed-point sums of rho^2
+// Fixed-point units of the spectrum sums (per offset s <= 1) and of the rho^2 sums per
+// template (rho^2 <= 1): 2^-32, so that a sum over the most offsets a series can have
+// (< 2^31) stays below 2^63 and a u64 accumulator cannot wrap.
+constexpr double SPEC_FIX_SCALE = 4294967296.0;     // 2^32
+constexpr double SIGMA_FIX_SCALE = 4294967296.0;    // 2^32
+constexpr int64_t MAX_SERIES_SAMPLES = (int64_t)1 << 31;
+static_assert((double)MAX_SERIES_SAMPLES * 1.001 * SPEC_FIX_SCALE < 9223372036854775808.0,
+              "spectrum sums cannot wrap");
+static_assert((double)MAX_SERIES_SAMPLES * 1.001 * SIGMA_FIX_SCALE < 9223372036854775808.0,
+              "rho^2 sums cannot wrap");
 
 enum Precision {
   P_FP32 = 0, P_BF16X3 = 1, P_FP8 = 2, P_F16X2 = 3, P_FFT = 4, P_F16F8 = 5, P_F16F6 = 6
@@ -94,16 +102,15 @@ struct SegDesc {
   int64_t tail_cap;
 };
 
-// The level subtracted from every staged sample.  Under the centred normalisation (norm 0) it
-// is the mean of the series over its finite samples, from its prefix sums, rounded to a
-// multiple of q = 2^floor(log2 sigma), sigma the series' standard deviation: a mean within
-// about one sigma of zero gives 0, so data that the forms hold exactly (a run of zeros) stays
-// exact, while a level far above the fluctuations is removed.  With zero-mean templates the
-// correlation does not depend on a constant, and the rounding of each form then acts on the
-// fluctuations.  Under the raw normalisation (which includes the level) and for a series with
-// no finite samples or no spread it is 0.
-__device__ inline float series_offset(const SegDesc& sg, int norm) {
-  if (norm != 0) return 0.0f;
+// The level subtracted from every staged sample: the mean of the series over its finite
+// samples, from its prefix sums, rounded to a multiple of q = 2^floor(log2 sigma), sigma the
+// series' standard deviation.  A mean within about one sigma of zero gives 0, so data that the
+// forms hold exactly (a run of zeros) stays exact, while a level far above the fluctuations is
+// removed.  With zero-mean templates the correlation does not depend on a constant, under
+// either normalisation (the window energy comes from the prefix sums of the series itself), so
+// each form rounds the fluctuations, not the level.  0 for a series with no finite samples or
+// no spread.
+__device__ inline float series_offset(const SegDesc& sg) {
   const int64_t good = sg.n - (int64_t)sg.cnt[sg.n];
   if (good <= 0) return 0.0f;
   const double mean = (sg.pre[4 * sg.n] + sg.pre[4 * sg.n + 1]) / (double)good;

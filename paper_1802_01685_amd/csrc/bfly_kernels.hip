@@ -928,12 +928,12 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
   const int64_t tile_hi = (k_hi + (32 * MB) - 1) / (32 * MB);
 
   // ---- strip fill ----
-  // Every form stages x - c, c the level from series_offset (the series mean under the centred
-  // normalisation): the correlation does not depend on c, and the rounding then acts on the
-  // fluctuations, not on a constant level.
+  // Every form stages x - c, c the level from series_offset (the rounded series mean): the
+  // correlation does not depend on c, and the rounding then acts on the fluctuations, not on a
+  // constant level.
   // Padding past the series end and non-finite samples stage as 0 in this shifted frame: they
   // reach only masked offsets, and a -c there would set the strip scale instead of the data.
-  const float c0 = series_offset(sg, p.norm);
+  const float c0 = series_offset(sg);
   auto xs = [&](int64_t gi) -> float {
     if (gi >= sg.n) return 0.0f;
     const float v = sg.x[gi];
@@ -1594,7 +1594,7 @@ hipError_t launch_main(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
 // ---------------------------------------------------------------------------------------
 // Finalise: m = f32(|d|max * inv_norm) in float64, argmax from the packed key, histogram of
 // m over non-degenerate windows (LDS-privatised), degenerate count, spectrum = fixed-point
-// sum / (2^40 W).
+// sum / (2^32 W).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(const BatchHdr* __restrict__ hdr, BankDev b,
                                                   SearchDev p) {

@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -73,6 +74,28 @@ struct TableInfo {
 };
 TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s, int32_t n,
                      int slots, BatchHdr* hdr);
+
+// The batch table of a single series, laid out as in the workspace ([BatchHdr][SegDesc]).
+struct OneSeriesTable {
+  BatchHdr hdr;
+  SegDesc seg;
+};
+static_assert(offsetof(OneSeriesTable, seg) == sizeof(BatchHdr), "table layout");
+
+// How a search's batch table reaches the device: copied from a pinned host staging buffer
+// (any batch), or written by a one-work-group kernel that takes the table of a single series
+// as its argument (no host or device allocation; bfly_noalloc.hip).
+enum class TableUpload { Staging, Kernel };
+hipError_t launch_put_table(const OneSeriesTable& t, OneSeriesTable* dst, hipStream_t s);
+
+// Validates a batch, lays it out in the workspace (table first), uploads the table and
+// enqueues the search (and, with tails, the tail passes) on stream.  With
+// TableUpload::Kernel, n_segs must be 1, the workspace is not checked with the pointer
+// query and no timing records are taken.
+bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
+                    const bf_search_params* prm, void* workspace, size_t ws_bytes,
+                    hipStream_t stream, const bf_tails* tails, float kappa,
+                    TableUpload upload);
 
 // Per-kernel timing records (optional; see bf_set_timing).
 struct TimingSet {

@@ -451,6 +451,107 @@ def pin_tails_invariants(o):
 
 
 # ---------------------------------------------------------------------------------------
+# several series at once, the top-2 margin, |rho| at given pairs
+# ---------------------------------------------------------------------------------------
+def _brute_reduce(rho, deg, kg, bins, nb, hist_bins=8):
+    """Reductions of a brute-force rho table, in plain loops: m, a (first maximum in
+    increasing k), the second largest |rho| (ties count twice), S, histogram."""
+    m, a, second, S = [], [], [], []
+    for row, d_ in zip(rho, deg):
+        if d_:
+            m.append(0.0)
+            a.append(-1)
+            second.append(0.0)
+            S.append([0.0] * nb)
+            continue
+        best, arg = -1.0, -1
+        Srow = [0.0] * nb
+        for k, v in enumerate(row):
+            if abs(v) > best:
+                best, arg = abs(v), kg[k]
+            Srow[bins[k]] = max(Srow[bins[k]], abs(v))
+        vals = sorted((abs(v) for v in row), reverse=True)
+        m.append(best)
+        a.append(arg)
+        second.append(vals[1] if len(vals) > 1 else -1.0)
+        S.append(Srow)
+    hist = [0] * hist_bins
+    for v, d_ in zip(m, deg):
+        if not d_:
+            hist[min(hist_bins - 1, max(0, int(math.floor(v * hist_bins))))] += 1
+    return np.array(m), np.array(a), np.array(second), np.array(S), np.array(hist)
+
+
+def pin_search_many_brute_force(o):
+    """Three series of uneven length (constant runs, a NaN) searched together on a sharded
+    bank, on all or on a subset of their offsets, with the bank applied in one, two or four
+    chunks: m, a, the runner-up |rho|, S and the histograms equal pure-Python loops, and each
+    series equals its own single search bit for bit."""
+    p = BankParams(fs=16.0, L=7, n_f0=8, n_fdot=3, f0_min=1.5, f0_max=6.0,
+                   fdot_min=-3.0, fdot_max=5.0, shard_index=1, shard_count=2)
+    rng = np.random.default_rng(21)
+    xs = [rng.standard_normal(40), 0.3 + 2.0 * rng.standard_normal(23), rng.standard_normal(31)]
+    xs[0][12:21] = 0.5              # windows 12..14 degenerate
+    xs[1][9] = np.nan               # windows 3..9 hold a NaN
+    xs[2][20:31] = 0.0              # windows 20..24 degenerate (all zero)
+    offs = [None, np.array([0, 2, 3, 9, 10, 16]), None]
+    for norm in ("centred", "raw"):
+        for kc in (3, 6, None):
+            many = o.search_many(xs, p, offs, norm=norm, hist_bins=8, k_chunk=kc)
+            for x, of, r in zip(xs, offs, many):
+                rho, deg, kg, bins = _brute_rho(x, p, norm)
+                sel = np.arange(len(rho)) if of is None else of
+                m, a, second, S, hist = _brute_reduce([rho[t] for t in sel],
+                                                      [deg[t] for t in sel], kg, bins, 4)
+                assert np.array_equal(r["offsets"], sel)
+                assert np.array_equal(r["degen"], np.array([deg[t] for t in sel]))
+                assert np.allclose(r["m"], m, rtol=0, atol=1e-13), (norm, kc)
+                assert np.array_equal(r["a"], a), (norm, kc, r["a"], a)
+                assert np.allclose(r["second"], second, rtol=0, atol=1e-13), (norm, kc)
+                assert np.allclose(r["S"], S, rtol=0, atol=1e-13)
+                assert np.array_equal(r["hist"], hist)
+                one = o.search(x, p, offsets=of, norm=norm, hist_bins=8, k_chunk=kc)
+                for key in ("m", "a", "second", "S", "hist", "spectrum", "degen"):
+                    assert np.array_equal(one[key], r[key]), (key, norm, kc)
+
+
+def pin_second_ties(o):
+    """Duplicate templates tie exactly: the runner-up equals the maximum (margin 0), within a
+    chunk and across chunks; with distinct templates the margin is positive."""
+    q = BankParams(fs=64.0, L=20, n_f0=2, n_fdot=3, f0_min=6.0, f0_max=6.0,
+                   fdot_min=1.0, fdot_max=1.0)
+    x = np.random.default_rng(22).standard_normal(120)
+    for kc in (3, 6):
+        r = o.search(x, q, k_chunk=kc)
+        assert np.array_equal(r["second"], r["m"])
+    p = _small_bank(L=20)
+    r = o.search(x, p)
+    assert np.all(r["m"] - r["second"] > 0)
+
+
+def pin_rho_at_brute_force(o):
+    """|rho| at given (offset, global template) pairs on a sharded bank against pure-Python
+    loops, with degenerate windows (0) and k = -1 entries (0), both norms."""
+    p = BankParams(fs=16.0, L=7, n_f0=5, n_fdot=3, f0_min=1.5, f0_max=4.0,
+                   fdot_min=-3.0, fdot_max=5.0, shard_index=1, shard_count=2)
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(40) - 0.8
+    x[15:24] = 1.5            # windows 15..17 degenerate (centred)
+    x[30] = np.inf            # windows 24..30 hold an inf
+    for norm in ("centred", "raw"):
+        rho, deg, kg, _ = _brute_rho(x, p, norm)
+        taus = rng.integers(0, len(rho), 60)
+        ks = rng.integers(0, len(kg), 60)
+        want = np.array([abs(rho[t][k]) for t, k in zip(taus, ks)])
+        kglob = np.array([kg[k] for k in ks])
+        kglob[::7] = -1
+        want[::7] = 0.0
+        got = o.rho_at(x, p, taus, kglob, norm=norm)
+        assert np.allclose(got, want, rtol=0, atol=1e-13), norm
+        assert np.any(got > 0) and np.all(got[np.array([deg[t] for t in taus])] == 0.0)
+
+
+# ---------------------------------------------------------------------------------------
 # two-detector coincidence of tails
 # ---------------------------------------------------------------------------------------
 def _brute_coincidences(ta, ka, tb, kb, p, dtau, df):

@@ -20,15 +20,15 @@ MUTANTS = {
     "dropped_half": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t + fdot * (t * t)"),
     "fdot_sign": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t - 0.5 * fdot * (t * t)"),
     "t_in_samples": ("t = np.arange(L, dtype=np.float64) / fs", "t = np.arange(L, dtype=np.float64)"),
-    "convolution": ("r = np.abs((Xw @ H.T) * scale[:, None])          # |rho|",
-                    "r = np.abs((Xw[:, ::-1] @ H.T) * scale[:, None])          # |rho|"),
+    "convolution": ('r = np.abs((q["Xw"] @ H.T) * q["scale"][:, None])          # |rho|',
+                    'r = np.abs((q["Xw"][:, ::-1] @ H.T) * q["scale"][:, None])          # |rho|'),
     "numerator_flip": ("    return Xw @ H.T\n", "    return Xw @ H[:, ::-1].T\n"),
     "raw_energy": ("dev = Xf - mu", "dev = Xf"),
-    "norm_not_sqrt": ("scale[~degen] = 1.0 / np.sqrt(E[~degen])\n\n    nb",
-                      "scale[~degen] = 1.0 / E[~degen]\n\n    nb"),
+    "norm_not_sqrt": ("scale[~degen] = 1.0 / np.sqrt(E[~degen])\n        series.append",
+                      "scale[~degen] = 1.0 / E[~degen]\n        series.append"),
     "argmax_last": ("j = np.argmax(r, axis=1)                          # first",
                     "j = r.shape[1] - 1 - np.argmax(r[:, ::-1], axis=1)  # first"),
-    "merge_ge": ("better = v > m", "better = v >= m"),
+    "merge_ge": ('better = v > q["m"]', 'better = v >= q["m"]'),
     "fdot_major": ("f0 = np.repeat(f0_axis[lo:hi], p.n_fdot)\n    fdot = np.tile(fd_axis, nb)",
                    "f0 = np.tile(f0_axis[lo:hi], p.n_fdot)\n    fdot = np.repeat(fd_axis, nb)"),
     "linspace_open": ("fd_axis = np.linspace(p.fdot_min, p.fdot_max, p.n_fdot)",
@@ -36,8 +36,8 @@ MUTANTS = {
     "shard_index": ("kg = lo * p.n_fdot + np.arange(nb * p.n_fdot)", "kg = np.arange(nb * p.n_fdot)"),
     "hist_round": ("q = np.floor(", "q = np.round("),
     "hist_with_degenerate": ("b = hist_bin(m[~degen], bins, lo, hi)", "b = hist_bin(m, bins, lo, hi)"),
-    "spec_transposed": ("S[:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)",
-                        "S[:, b0:b1] = r.reshape(T, nfd, b1 - b0).max(axis=1)"),
+    "spec_transposed": ('q["S"][:, b0:b1] = r.reshape(T, b1 - b0, nfd).max(axis=2)',
+                        'q["S"][:, b0:b1] = r.reshape(T, nfd, b1 - b0).max(axis=1)'),
     "nan_not_degenerate": ("degen = (~finite) | (R == 0.0)", "degen = (R == 0.0)"),
     "no_rel_threshold": ("| (E <= DEGENERATE_REL * R)", "| (E < 0.0)"),
     "window_shift": ("return v if offsets is None else v[np.asarray(offsets)]",
@@ -56,6 +56,26 @@ MUTANTS = {
     "tails_local_index": ("ks.append(g.k_global[k0 + j])", "ks.append(k0 + j)"),
     "tail_counts_by_fdot": ("counts += np.bincount(g.bin[k0 + j], minlength=g.n_bins)",
                             "counts += np.bincount((k0 + j) // nfd % g.n_bins, minlength=g.n_bins)[::-1]"),
+    "many_chunk_offset": ('q["a"][better] = g.k_global[k0 + j[better]]',
+                          'q["a"][better] = g.k_global[j[better]]'),
+    "many_degenerate_argmax": ("        a[degen] = -1\n        S[degen] = 0.0",
+                               "        S[degen] = 0.0"),
+    "many_mixed_series": ('r = np.abs((q["Xw"] @ H.T) * q["scale"][:, None])',
+                          'r = np.abs((q["Xw"] @ H.T) * series[0]["scale"][:1, None])'),
+    "second_forgets_smaller_max": (
+        'q["second"] = np.maximum(np.minimum(q["m"], v), np.maximum(q["second"], c2))',
+        'q["second"] = np.maximum(q["second"], c2)'),
+    "second_is_smaller_max": (
+        'q["second"] = np.maximum(np.minimum(q["m"], v), np.maximum(q["second"], c2))',
+        'q["second"] = np.minimum(q["m"], v)'),
+    "second_third_largest": ("c2 = np.partition(r, -2, axis=1)[:, -2] if k1 - k0 > 1",
+                             "c2 = np.partition(r, -3, axis=1)[:, -3] if k1 - k0 > 2"),
+    "rho_at_local_index": ("kl = kg[ok] - int(g.k_global[0])", "kl = kg[ok]"),
+    "rho_at_signed": ("r[~degen] = np.abs(d[~degen]) / np.sqrt(E[~degen])",
+                      "r[~degen] = d[~degen] / np.sqrt(E[~degen])"),
+    "rho_at_not_degenerate": ("r[~degen] = np.abs(d[~degen]) / np.sqrt(E[~degen])",
+                              "r = np.abs(d) / np.sqrt(np.maximum(E, 1e-300))"),
+    "rho_at_window_shift": ("Xw = windows(x, p.L, offs[ok])", "Xw = windows(x, p.L, offs[ok] + 1)"),
     "coinc_strict_df": ("if abs(fa[i] - fb[j]) <= df:", "if abs(fa[i] - fb[j]) < df:"),
     "coinc_no_dtau": ("for t in range(int(ta[i]) - dtau, int(ta[i]) + dtau + 1):",
                       "for t in range(int(ta[i]), int(ta[i]) + 1):"),
