@@ -264,7 +264,7 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     if (segs[i].n < b.L)
       return fail(BF_EINVAL, "series %d has %lld samples, fewer than L = %d", i,
                   (long long)segs[i].n, b.L);
-    if (segs[i].n > ((int64_t)1 << 31) - MAX_N_WG - b.L_pad - STRIP_SLACK)
+    if (segs[i].n > MAX_SERIES_SAMPLES - MAX_N_WG - b.L_pad - STRIP_SLACK)
       return fail(BF_EINVAL, "series %d is too long", i);
     if (!segs[i].x) return fail(BF_EINVAL, "series %d: x is NULL", i);
   }

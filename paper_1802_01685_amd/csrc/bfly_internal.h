@@ -26,10 +26,10 @@ constexpr int MAX_F16F8_L = 4224;            // F16F8, F16F6: 24-byte strip cell
                                              // fill 160 KB LDS
 constexpr int MAX_HIST_BINS = 4096;
 // Fixed-point units of the spectrum sums (per offset s <= 1) and of the rho^2 sums per
-// template (rho^2 <= 1): 2^-32, so that a sum over the most offsets a series can have
+// template (rho^2 <= 1): 2^-31, so that a sum over the most offsets a series can have
 // (< 2^31) stays below 2^63 and a u64 accumulator cannot wrap.
-constexpr double SPEC_FIX_SCALE = 4294967296.0;     // 2^32
-constexpr double SIGMA_FIX_SCALE = 4294967296.0;    // 2^32
+constexpr double SPEC_FIX_SCALE = 2147483648.0;     // 2^31
+constexpr double SIGMA_FIX_SCALE = 2147483648.0;    // 2^31
 constexpr int64_t MAX_SERIES_SAMPLES = (int64_t)1 << 31;
 static_assert((double)MAX_SERIES_SAMPLES * 1.001 * SPEC_FIX_SCALE < 9223372036854775808.0,
               "spectrum sums cannot wrap");
