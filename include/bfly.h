@@ -63,24 +63,28 @@ typedef enum {
   BF_BF16X3 = 1, /* bf16 hi+lo split of templates and data; hi*hi + hi*lo + lo*hi */
   BF_FP8 = 2,    /* OCP e4m3 templates and data with power-of-two scales (per template, per
                     strip), undone by the MFMA scale operands; the rounded templates' sums
-                    times the window mean are subtracted.  ~1% median, <=25% worst-case
-                    relative error (short templates) */
+                    times the window mean are subtracted.  Bound from the rounding model
+                    (e4m3, 2^-4 per operand, six standard deviations): 0.43 of the noise
+                    scale 1/sqrt(L) of |rho|; ~1% median relative error */
   BF_F16X2 = 3,  /* fp16 hi+lo split of the templates, fp16 data with a power-of-two strip
                     scale; h_hi*x + h_lo*x (two MFMA products per tap).  The data's fp16
-                    rounding bounds the error: ~1e-4 to 7e-4 relative, stated bound
-                    1e-3 */
+                    rounding (2^-11) bounds the error: 2.4e-3 of the noise scale */
   BF_FFT = 4,    /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
                     real FFTs of length N = 2M, M in 512..4096 minimising M log2 M per valid
-                    output (N - L + 1); L <= 4096; the same outputs as the direct forms */
+                    output (N - L + 1); L <= 4096; the same outputs as the direct forms.
+                    Bound 1e-5, growing as 3.2e-6 x (RMS of the loudest transform block
+                    near the window / the window's RMS) where that ratio exceeds ~3 */
   BF_F16F8 = 5,  /* fp16 product of the fp16-rounded template and data, plus the two residual
                     products (template residual x data, template x data residual) as e4m3 codes
                     with power-of-two scales (per template, per strip) undone by the MFMA scale
                     operands; the rounded templates' sums times the window mean are
                     subtracted.  Two thirds of BF_BF16X3's MFMA time per tap; ~1e-5 to 3e-5
-                    relative error, stated bound 1e-4; L <= 4224 */
+                    relative error, bound 1e-4; L <= 4224 */
   BF_F16F6 = 6   /* as BF_F16F8 with the residual products in e2m3 (fp6) codes, whose MFMA
                     runs at twice the e4m3 rate: half of BF_BF16X3's MFMA time per tap.
-                    Stated bound 1e-4; L <= 4224 */
+                    Bound 1e-4, growing as 2.8e-5 x (largest sample near the window / the
+                    window's RMS) up to BF_F16X2's 2.4e-3: the data residual codes have a
+                    fixed quantum within a strip; L <= 4224 */
 } bf_precision;
 
 typedef enum { BF_NORM_CENTRED = 0, BF_NORM_RAW = 1 } bf_norm;
