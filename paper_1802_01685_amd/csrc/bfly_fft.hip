@@ -80,6 +80,21 @@ __device__ __forceinline__ float2 twiddle16(float2 b) {
   }
 }
 
+// twiddle16 for a q that is a constant after unrolling.
+template <bool INV>
+__device__ __forceinline__ float2 twiddle16_q(float2 b, int q) {
+  switch (q) {
+    case 0: return twiddle16<0, INV>(b);
+    case 1: return twiddle16<1, INV>(b);
+    case 2: return twiddle16<2, INV>(b);
+    case 3: return twiddle16<3, INV>(b);
+    case 4: return twiddle16<4, INV>(b);
+    case 5: return twiddle16<5, INV>(b);
+    case 6: return twiddle16<6, INV>(b);
+    default: return twiddle16<7, INV>(b);
+  }
+}
+
 // One radix-2 stage of span S (s in the DIT recursion) over t[], groups of S from offset G.
 template <int R, int S, int G, int K, bool INV>
 __device__ __forceinline__ void dft_bfly(float2 (&t)[R]) {
@@ -567,6 +582,391 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// The search kernel at M = 4096 (real FFTs of N = 8192 points; the length the planner picks
+// for templates of roughly 1,500 to 4,096 taps).  One transform per work-group of 256
+// threads (one wave per SIMD), 16 points per thread, two work-groups per CU:
+// * The thread owns inverse-FFT butterflies j0 = t and j1 = 512 - t of the first radix-8
+//   pass, whose points j + 512 r are closed under the mirror p -> M - p of the real-FFT
+//   post-processing.  It keeps the data spectrum X_b at those points in registers for the
+//   whole work item, loads H_k at the same points (the next template's while the current
+//   one is transformed), and forms Y = E + iO and the first pass's radix-8 DFTs in registers:
+//   the spectrum product never goes through LDS.  (Thread 0's butterflies, 0 and 256, are
+//   each their own mirror; lanes 0..3 of wave 0 form butterfly 256's four pairs and hand the
+//   values to thread 0 through LDS.)
+// * Passes 2..4 run two radix-8 butterflies per thread with their twiddle powers held in
+//   registers, ping-ponging between two LDS buffers: three barriers per template.
+// * The last pass leaves the thread 16 complex outputs = 32 real outputs at offsets
+//   2t + 512 s + part (s < 16); only the first SMAX slots can hold valid offsets
+//   (SMAX >= (2M - L + 1) / 512).  Per output the thread keeps the running maximum over the
+//   current f0 bin and the template reaching it; at the end of a bin it writes the
+//   spectrogram row, adds to the spectrum sums and merges (bin maximum, template) into the
+//   per-offset packed maxima with one atomic max each.  That is the same merge as the other
+//   forms (value first, then the lower template), so the results do not depend on how the
+//   bank is split into bins and ranges.
+// The sigma and tails modes are those of k_fft_main.
+namespace fft4k {
+constexpr int M = 4096;
+constexpr int PADN = M + M / 8;
+constexpr unsigned ROW_BYTES = (M + 2) * 8;   // one spectrum row (bins 0..M, padded)
+}  // namespace fft4k
+
+// A buffer resource on one spectrum row: the loads below address it with a 32-bit per-lane
+// byte offset and a uniform (SGPR) byte offset, so a row needs no per-lane 64-bit address
+// arithmetic; reads past the row return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float2* row) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(row), (short)0,
+                                           (int)fft4k::ROW_BYTES, 0x00020000);
+}
+__device__ __forceinline__ float2 row_load(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                           unsigned soff) {
+  const float re = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  const float im =
+      __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff + 4u, soff, 0));
+  return make_float2(re, im);
+}
+
+// The spectrum product and the inverse real-FFT post-processing of one mirror pair
+// (a, M - a): from C1 = conj(H[a]) X[a] and C2 = conj(H[M - a]) X[M - a], with
+// w = exp(+2 pi i a / N), Y[a] = E + iO and Y[M - a] = E* + iO* (both twice their value;
+// the 1/2 is in the output scale).
+__device__ __forceinline__ void mirror_pair(float2 ha, float2 xa, float2 hb, float2 xb,
+                                            float2 w, float2& ya, float2& yb) {
+  const float2 c1 = cmul(cconj(ha), xa);
+  const float2 c2 = cmul(cconj(hb), xb);
+  const float2 e = cadd(c1, cconj(c2));
+  const float2 d = csub(c1, cconj(c2));
+  const float2 o = cmul(d, w);
+  ya = make_float2(e.x - o.y, e.y + o.x);
+  yb = make_float2(e.x + o.y, o.x - e.y);
+}
+
+// One radix-8 Stockham pass of two butterflies (t and t + 256) from `src` to `dst` with
+// sub-transform size NS before the pass; input r of butterfly t is twiddled by wa[r - 1] and
+// of butterfly t + 256 by wb[r - 1].  KEEP leaves the outputs in y0, y1 instead of writing
+// them.
+template <int NS, bool KEEP>
+__device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* __restrict__ dst,
+                                        const float2 (&wa)[7], const float2 (&wb)[7],
+                                        float2 (&y0)[8], float2 (&y1)[8]) {
+  const int t = threadIdx.x;
+  // pad(t + 512 r) = pad(t) + 576 r and pad(t + 256 + 512 r) = pad(t) + 288 + 576 r
+  const float2* rd = src + pad(t);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    y0[r] = rd[576 * r];
+    y1[r] = rd[288 + 576 * r];
+  }
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    y0[r] = cmul(y0[r], wa[r - 1]);
+    y1[r] = cmul(y1[r], wb[r - 1]);
+  }
+  dft<8, true>(y0);
+  dft<8, true>(y1);
+  if constexpr (!KEEP) {
+    // output r of butterfly j goes to point o + r NS, o = (j - j mod NS) 8 + j mod NS; NS is a
+    // multiple of 8, so pad(o + r NS) = pad(o) + r (NS + NS / 8)
+    const int m0 = t & (NS - 1), m1 = (t + 256) & (NS - 1);
+    float2* w0 = dst + pad((t - m0) * 8 + m0);
+    float2* w1 = dst + pad((t + 256 - m1) * 8 + m1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      w0[r * (NS + NS / 8)] = y0[r];
+      w1[r * (NS + NS / 8)] = y1[r];
+    }
+  }
+}
+
+template <int SMAX, int MODE>
+__global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
+                                                  SearchDev p) {
+  using namespace fft4k;
+  static_assert(SMAX >= 1 && SMAX <= 16, "output slots");
+  constexpr int NO = 2 * SMAX;          // real outputs per thread that can be valid
+  __shared__ float2 lds[2 * PADN];
+  __shared__ float2 hand[8];            // butterfly 256's first-pass inputs for thread 0
+  __shared__ float2 hand_x[8];          // X_b at the helpers' pairs
+  // twiddle powers of passes 2 and 3, w^r = exp(2 pi i (j mod NS) r / (8 NS)) for
+  // j mod NS = m: entry [(r - 1) NS + m] (lanes read consecutive entries)
+  __shared__ float2 tab2[7 * 8];
+  __shared__ float2 tab3[7 * 64];
+  const SegDesc* segs = hdr_segs(hdr);
+  const float2* spectra = (const float2*)b.data;
+  const int n_ranges = hdr->n_ranges;
+  const int64_t n_items = hdr->n_items;
+  const int valid = 2 * M - b.L + 1;
+  const int t = threadIdx.x;
+  const float scale = 0.5f / (float)M;
+  const int nfd = b.n_fdot;
+
+  // first-pass butterflies j0 = t and j1 = 512 - t (thread 0: 0, and 256 handed over);
+  // pair r = (a_r, M - a_r) with a_r = t + 512 r; its post-processing twiddle
+  float2 wpair[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) wpair[r] = cis_rev<true>((float)(t + 512 * r) / (float)(2 * M));
+  // lanes 0..3 of wave 0: pair (256 + 512 t, M - 256 - 512 t) of butterfly 256
+  const bool helper = t < 4;
+  const int ha_idx = 256 + 512 * (t & 3);
+  const float2 whelp = cis_rev<true>((float)ha_idx / (float)(2 * M));
+  const int j1w = t == 0 ? 256 : 512 - t;   // butterfly written from v1
+  // twiddle powers: passes 2 (NS = 8) and 3 (NS = 64) from the LDS tables, pass 4 (NS = 512,
+  // butterflies t and t + 256) in registers
+  for (int i = t; i < 7 * 64; i += 256) {
+    const int r = i / 64 + 1, m = i % 64;
+    tab3[i] = cis_rev<true>((float)((m * r) & 511) / 512.0f);
+    if (i < 7 * 8) {
+      const int r2 = i / 8 + 1, m2 = i % 8;
+      tab2[i] = cis_rev<true>((float)((m2 * r2) & 63) / 64.0f);
+    }
+  }
+  float2 tw4a[7], tw4b[7];
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    tw4a[r - 1] = cis_rev<true>((float)((t * r) & 4095) / 4096.0f);
+    tw4b[r - 1] = cis_rev<true>((float)(((t + 256) * r) & 4095) / 4096.0f);
+  }
+  __syncthreads();
+
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int rg = (int)(item % n_ranges);
+    const int64_t tt = item / n_ranges;
+    int lo = 0, hi = hdr->n_segs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
+    }
+    const SegDesc& sg = segs[lo];
+    const int64_t blk = tt - sg.tile0;
+    const int tau_base = (int)(blk * valid);     // series are shorter than 2^31 samples
+    const int b_lo = (int)((int64_t)rg * b.n_bins / n_ranges);
+    const int b_hi = (int)((int64_t)(rg + 1) * b.n_bins / n_ranges);
+    const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
+    // bins a_r = t + 512 r at byte 8t + 4096 r; bins M - a_r at 8 (512 - t) + 4096 (7 - r)
+    const unsigned va = 8u * (unsigned)t, vb = 8u * (512u - (unsigned)t);
+    float2 xa[8], xb[8];
+    {
+      const __amdgpu_buffer_rsrc_t xr = row_rsrc(xsrc);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        xa[r] = row_load(xr, va, 4096u * r);
+        xb[r] = row_load(xr, vb, 4096u * (7 - r));
+      }
+    }
+    // X at the helpers' pairs, kept in LDS (read by the helper lanes only)
+    if (helper) {
+      hand_x[2 * t] = xsrc[ha_idx];
+      hand_x[2 * t + 1] = xsrc[M - ha_idx];
+    }
+    // output o = 2 s + part sits at block position 2t + 512 s + part; it is a valid offset of
+    // the series below this bound
+    const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
+    float binmax[NO];
+    int binarg[NO];
+    float inv[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      if constexpr (MODE == MODE_SEARCH) {
+        binmax[o] = -1.0f;
+        binarg[o] = -1;
+      } else {
+        const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
+        inv[o] = pos < pos_end ? (float)sg.inv_norm[tau_base + pos] : 0.0f;
+      }
+    }
+    const int k_lo = b_lo * nfd, k_hi = b_hi * nfd;
+    float2 ha[8], hb[8], hha = make_float2(0.0f, 0.0f), hhb = hha;
+    auto load_h = [&](int k) {
+      const float2* hk = spectra + (int64_t)k * (M + 2);
+      const __amdgpu_buffer_rsrc_t hr = row_rsrc(hk);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        ha[r] = row_load(hr, va, 4096u * r);
+        hb[r] = row_load(hr, vb, 4096u * (7 - r));
+      }
+      // every lane loads the helpers' pair (only lanes 0..3 of wave 0 use it): a load under
+      // a lane condition would make the prefetch wait at the join
+      hha = row_load(hr, 8u * (unsigned)ha_idx, 0u);
+      hhb = row_load(hr, 8u * (unsigned)(M - ha_idx), 0u);
+    };
+    load_h(k_lo);
+    int bin = b_lo, left = nfd;
+    float2* bufp = lds;            // pass 1 writes here; the buffers swap every template
+    float2* bufq = lds + PADN;
+    for (int k = k_lo; k < k_hi; ++k) {
+      // ---- spectrum product, post-processing and the first radix-8 pass, in registers
+      float2 v0[8], v1[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        mirror_pair(ha[r], xa[r], hb[r], xb[r], wpair[r], v0[r], v1[7 - r]);
+      if (helper) {
+        float2 ya, yb;
+        mirror_pair(hha, hand_x[2 * t], hhb, hand_x[2 * t + 1], whelp, ya, yb);
+        hand[t] = ya;
+        hand[7 - t] = yb;
+      }
+      load_h(min(k + 1, k_hi - 1));   // unconditional (the last one repeats a row)
+      if (t == 0) {
+        // the helpers are lanes of this wave: their LDS writes precede these reads
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v1[r] = hand[r];
+      }
+      dft<8, true>(v0);
+      dft<8, true>(v1);
+      // point 8 j + r of the first pass's output: pad = 9 j + r
+      float2* w0 = bufp + 9 * t;
+      float2* w1 = bufp + 9 * j1w;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        w0[r] = v0[r];
+        w1[r] = v1[r];
+      }
+      __syncthreads();
+      float2 y0[8], y1[8];
+      {
+        float2 w[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
+        pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
+      }
+      __syncthreads();
+      {
+        float2 w[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) w[r] = tab3[64 * r + (t & 63)];
+        pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
+      }
+      __syncthreads();
+      pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+      {
+        float2* s = bufp;
+        bufp = bufq;
+        bufq = s;
+      }
+      // output slot o = 2 s + part: s even -> y0[s / 2], s odd -> y1[s / 2]
+      auto outv = [&](int o) -> float {
+        const int s = o >> 1;
+        const float2 c = (s & 1) ? y1[s >> 1] : y0[s >> 1];
+        return (o & 1) ? c.y : c.x;
+      };
+      if constexpr (MODE == MODE_SIGMA) {
+        float q = 0.0f;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          const float rr = (float)((double)(outv(o) * scale) * (double)inv[o]);
+          q = fmaf(rr, rr, q);
+        }
+        unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const unsigned flo = __shfl_xor((unsigned)(f & 0xFFFFFFFFull), o, 64);
+          const unsigned fhi = __shfl_xor((unsigned)(f >> 32), o, 64);
+          f += ((unsigned long long)fhi << 32) | flo;
+        }
+        if ((t & 63) == 0 && f != 0ull) atomicAdd(sg.sig_acc + k, f);
+        continue;
+      }
+      if constexpr (MODE == MODE_TAILS) {
+        const float thr = sg.thr[k];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          const float rf = (float)((double)(outv(o) * scale) * (double)inv[o]);
+          if (fabsf(rf) > thr) {
+            const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
+            if ((int64_t)slot < sg.tail_cap) {
+              sg.t_tau[slot] = tau_base + 2 * t + 512 * (o >> 1) + (o & 1);
+              sg.t_k[slot] = (int32_t)(b.k_offset + k);
+              sg.t_rho[slot] = rf;
+            }
+            atomicAdd(sg.t_bins + k / nfd, 1u);
+          }
+        }
+        continue;
+      }
+      // running maximum over the bin's templates, lowest k on ties (k increases, strict >)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        const float a = fabsf(outv(o));
+        const bool g = a > binmax[o];
+        binarg[o] = g ? k : binarg[o];
+        binmax[o] = g ? a : binmax[o];
+      }
+      if (--left == 0) {
+        // end of bin: spectrogram row, spectrum sum, packed per-offset maxima
+        unsigned long long fix = 0ull;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
+          if (pos < pos_end && binarg[o] >= 0) {
+            const int tau = tau_base + pos;
+            const float v = binmax[o] * scale;
+            const double iv = sg.inv_norm[tau];
+            if (iv > 0.0) {
+              const float s = (float)((double)v * iv);
+              if (sg.spec) {
+                const int row = p.t_block == 1 ? tau : tau / p.t_block;
+                const int64_t at = (int64_t)bin * sg.spec_rows + row;
+                if (p.t_block == 1)
+                  sg.spec[at] = s;
+                else
+                  atomicMax((unsigned int*)sg.spec + at, __float_as_uint(s));
+              }
+              fix += (unsigned long long)__double2ll_rn((double)s * SPEC_FIX_SCALE);
+            }
+            const unsigned int kg = (unsigned int)(b.k_offset + binarg[o]);
+            atomicMax(sg.mkey + tau,
+                      ((unsigned long long)__float_as_uint(v) << 32) | (0xFFFFFFFFull - kg));
+          }
+          binmax[o] = -1.0f;
+          binarg[o] = -1;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const unsigned flo = __shfl_xor((unsigned)(fix & 0xFFFFFFFFull), o, 64);
+          const unsigned fhi = __shfl_xor((unsigned)(fix >> 32), o, 64);
+          fix += ((unsigned long long)fhi << 32) | flo;
+        }
+        if ((t & 63) == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
+        ++bin;
+        left = nfd;
+      }
+    }
+  }
+}
+
+// Output slots of the M = 4096 kernel for valid = 2M - L + 1 offsets per block.
+inline int fft4k_slots(const BankDev& b) {
+  const int need = (2 * 4096 - b.L + 1 + 511) / 512;
+  return need <= 9 ? 9 : need <= 13 ? 13 : 16;
+}
+
+// BF_FFT_V1=1 runs the M = 4096 searches on k_fft_main instead (a comparison knob; the
+// results agree to the float32 bound, not bit for bit).
+bool fft4k_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("BF_FFT_V1");
+    return !(e && e[0] == '1');
+  }();
+  return on;
+}
+
+template <int MODE>
+hipError_t launch_fft4k(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
+                        const SearchDev& p, hipStream_t s) {
+  switch (fft4k_slots(b)) {
+    case 9:
+      hipLaunchKernelGGL((k_fft4k<9, MODE>), dim3((unsigned)blocks), dim3(256), 0, s, hdr, b, p);
+      break;
+    case 13:
+      hipLaunchKernelGGL((k_fft4k<13, MODE>), dim3((unsigned)blocks), dim3(256), 0, s, hdr, b, p);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fft4k<16, MODE>), dim3((unsigned)blocks), dim3(256), 0, s, hdr, b, p);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // Register target of the search kernel: BF_FFT_OCC=4 selects the 4-waves-per-SIMD build
 // (a tuning knob; results do not depend on it), else 2.
 int fft_occupancy() {
@@ -591,6 +991,7 @@ hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDe
   hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (M == 4096 && fft4k_enabled()) return launch_fft4k<MODE_SEARCH>(hdr, blocks, b, p, s);
   if (fft_occupancy() == 4)
     hipLaunchKernelGGL((k_fft_main<M, 4, MODE_SEARCH>), dim3((unsigned)blocks),
                        dim3(Plan<M>::T), 0, s, hdr, b, p);
@@ -604,6 +1005,11 @@ hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDe
 template <int M>
 hipError_t launch_fft_pass_t(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                              const SearchDev& p, hipStream_t s) {
+  if (M == 4096 && fft4k_enabled()) {
+    if (p.mode == MODE_SIGMA) return launch_fft4k<MODE_SIGMA>(hdr, blocks, b, p, s);
+    if (p.mode == MODE_TAILS) return launch_fft4k<MODE_TAILS>(hdr, blocks, b, p, s);
+    return hipErrorInvalidValue;
+  }
   if (p.mode == MODE_SIGMA)
     hipLaunchKernelGGL((k_fft_main<M, 2, MODE_SIGMA>), dim3((unsigned)blocks),
                        dim3(Plan<M>::T), 0, s, hdr, b, p);
