@@ -421,7 +421,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fft", choices=FORMS,
                     help="the headline form (value, roofline)")
     ap.add_argument("--form-steps", type=int, default=5,
-                    help="timed steps of each other form on the headline batch (>= 5)")
+                    help="timed steps of each other form on the headline batch")
     ap.add_argument("--forms", default=",".join(FORMS),
                     help="forms timed beside the headline ('' skips)")
     ap.add_argument("--cpu-offsets", type=int, default=1024,
@@ -483,7 +483,7 @@ def main() -> int:
         f"kernels {main_res['kernel_ms']}")
     forms = {}
     for form in [f for f in args.forms.split(",") if f and f != args.precision]:
-        n = max(5, args.form_steps)
+        n = max(1, args.form_steps)
         log(f"{form}: 1 warmup + {n} steps")
         forms[form] = time_form(bf, torch, p, xs, form, n, 1, keep)
         log(f"  {forms[form]['value']:.4g} corr/s, {forms[form]['ms_per_step']:.1f} ms/step")

@@ -459,6 +459,23 @@ int32_t plan_fft_ranges(const BankDev& b, int64_t total_tiles, int slots) {
   double best_cost = 1e300;
   int32_t best_r = 1;
   const int64_t conc = 2 * (int64_t)slots;
+  if (b.fft_m == 4096 && b.n_bins >= 8) {
+    // The N = 8192 kernel (two work-groups per CU) deals each XCD whole ranges when their
+    // count is a multiple of 8: cost = the XCD's rounds of items x bins per range.
+    const int64_t per_xcd = conc / 8;
+    for (int32_t r = 8; r <= b.n_bins; r += 8) {
+      const int64_t items = total_tiles * r;
+      if (items > (int64_t)0x7FFFFFFF) break;
+      const int64_t rounds = (total_tiles * (r / 8) + per_xcd - 1) / per_xcd;
+      const double cost = (double)rounds * (double)((b.n_bins + r - 1) / r) + 0.01 * (double)rounds;
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best_r = r;
+      }
+      if (items > 16 * conc) break;
+    }
+    return best_r;
+  }
   for (int32_t r = 1; r <= b.n_bins; ++r) {
     const int64_t items = total_tiles * r;
     if (items > (int64_t)0x7FFFFFFF) break;

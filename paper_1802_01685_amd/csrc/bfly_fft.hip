@@ -728,9 +728,22 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
   }
   __syncthreads();
 
+  const int64_t total_tiles = hdr->total_tiles;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const int rg = (int)(item % n_ranges);
-    const int64_t tt = item / n_ranges;
+    // Work-group i runs on XCD i mod 8 and each XCD takes its work-groups in order of i / 8.
+    // With 8m ranges, XCD x sweeps its ranges x, x + 8, ... one after another, blocks
+    // fastest, so the work-groups resident on an XCD sweep one range's spectra in step and
+    // share them through its L2; with other counts, range fastest.
+    int rg;
+    int64_t tt;
+    if (n_ranges % 8 == 0) {
+      const int64_t j = item / 8;
+      rg = (int)(item % 8) + 8 * (int)(j / total_tiles);
+      tt = j % total_tiles;
+    } else {
+      rg = (int)(item % n_ranges);
+      tt = item / n_ranges;
+    }
     int lo = 0, hi = hdr->n_segs - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
