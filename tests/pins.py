@@ -290,6 +290,27 @@ def pin_spectrogram_histogram(o):
     assert np.allclose(r["S"], want, rtol=0, atol=1e-13)
 
 
+def pin_average_spectrum(o):
+    """The multi-series average is the mean of each series' own time mean of S (reading 10,
+    Fig. 1 caption): pure-Python loops over series of uneven length, which differ from the
+    mean pooled over all offsets."""
+    p = _small_bank(L=16)
+    rng = np.random.default_rng(24)
+    xs = [rng.standard_normal(n) * s for n, s in ((90, 1.0), (400, 3.0), (150, 0.5))]
+    rs = [o.search(x, p) for x in xs]
+    got = o.average_spectrum([r["spectrum"] for r in rs])
+    want = []
+    for i in range(p.n_f0):
+        per = []
+        for r in rs:
+            col = [float(row[i]) for row in r["S"]]
+            per.append(sum(col) / len(col))
+        want.append(sum(per) / len(per))
+    assert np.allclose(got, want, rtol=1e-14, atol=0)
+    pooled = np.concatenate([r["S"] for r in rs]).mean(axis=0)
+    assert not np.allclose(got, pooled, rtol=1e-6, atol=0)
+
+
 def pin_degenerate_rule(o):
     """Constant, all-zero and NaN windows are degenerate; a tiny non-constant one is not."""
     L = 8

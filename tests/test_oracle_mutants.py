@@ -16,6 +16,8 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                    "oracle", "bfly_oracle.py")
 
 MUTANTS = {
+    "average_pooled": ("return np.mean(np.stack(spectra), axis=0)",
+                       "return np.mean(np.stack(spectra), axis=0) * 0 + np.median(np.stack(spectra), axis=0)"),
     "no_mean_removal": ("c = c - c.mean(axis=1, keepdims=True)", "c = c"),
     "dropped_half": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t + fdot * (t * t)"),
     "fdot_sign": ("phi = f0 * t + 0.5 * fdot * (t * t)", "phi = f0 * t - 0.5 * fdot * (t * t)"),
