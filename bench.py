@@ -203,6 +203,7 @@ def roofline(res, p, prec, tile):
     import math
     ms = res["kernel_ms"]["main"]
     traffic = recorded_traffic(prec, tile, "light_curve_share")
+    counters = recorded_counters(prec, tile, "light_curve_share")
     if prec == "fft":
         m = fft_points(p.L)
         valid = 2 * m - p.L + 1
@@ -211,7 +212,7 @@ def roofline(res, p, prec, tile):
         achieved = flops / (ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fft"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fft"], 4),
-                "traffic": traffic, "kernel": "k_fft_data+k_fft_main",
+                "traffic": traffic, "counters": counters, "kernel": "k_fft_data+k_fft4k",
                 "kernel_ms": round(ms, 3), "fft_points": 2 * m, "valid_per_block": valid,
                 "flop_per_launch": flops,
                 "effective_vs_fp32_peak": round(2.0 * p.L * res["corr_per_step"] /
@@ -220,7 +221,8 @@ def roofline(res, p, prec, tile):
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": "k_main",
+            "frac": round(achieved / peak, 4), "traffic": traffic, "counters": counters,
+            "kernel": "k_main",
             "kernel_ms": round(ms, 3), "mfma_terms": MFMA_TERMS[prec],
             "executed_frac": round(achieved * MFMA_TERMS[prec] / peak, 4),
             "flop_per_launch": flops,
@@ -239,11 +241,11 @@ def kernel_tile(prec):
     return "2x8i" if prec in ("bf16x3", "f16x2") else "2x4"
 
 
-def recorded_traffic(prec, tile, workload):
-    """HBM bytes per launch of the form's dominant kernel from the committed counter record
-    (FETCH_SIZE and WRITE_SIZE passes, scaled by the same counters on a copy of known size),
-    if it was taken on this workload and on exactly the current kernel source and tile; else
-    None.  The hash covers the kernel file followed by the internal header it includes."""
+def _record(kind, prec, tile, workload):
+    """The committed `kind` record (a line "<kind>: {json}" in a profiles/ summary) of the
+    form's dominant kernel, if it was taken on this workload and on exactly the current
+    kernel source and tile; else None.  The hash covers the kernel file followed by the
+    internal header it includes."""
     import glob
     import hashlib
     kernel_file = "bfly_fft.hip" if prec == "fft" else "bfly_kernels.hip"
@@ -254,7 +256,7 @@ def recorded_traffic(prec, tile, workload):
     sha = h.hexdigest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
-            if not line.startswith("traffic-record:"):
+            if not line.startswith(kind + ":"):
                 continue
             try:
                 rec = json.loads(line.split(":", 1)[1])
@@ -262,8 +264,24 @@ def recorded_traffic(prec, tile, workload):
                 continue
             if rec.get("kernel_sha256") == sha and rec.get("precision") == prec \
                     and rec.get("tile") == tile and rec.get("workload") == workload:
-                return rec["fetch_bytes"] + rec["write_bytes"]
+                return rec
     return None
+
+
+def recorded_traffic(prec, tile, workload):
+    """HBM bytes per launch from the committed counter record (FETCH_SIZE and WRITE_SIZE
+    passes, scaled by the same counters on a copy of known size), or None."""
+    rec = _record("traffic-record", prec, tile, workload)
+    return None if rec is None else rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def recorded_counters(prec, tile, workload):
+    """MFMA busy fraction, shader clock and VALU issue fraction of the same launches from the
+    committed counter record, or None."""
+    rec = _record("counter-record", prec, tile, workload)
+    if rec is None:
+        return None
+    return {k: rec[k] for k in ("mfma_busy", "clock_mhz", "valu_issue") if k in rec}
 
 
 def errors(orcs, kept, p, prec):
