@@ -229,17 +229,25 @@ typedef struct {
   bf_tails tails;
 } bf_tail_segment;
 
-/* Device workspace bytes of a tail search (bf_workspace_bytes plus K_pad * 12 bytes and
- * change per series). */
+/* Device workspace bytes of a tail search: bf_workspace_bytes plus, per series, the rho^2
+ * sums and thresholds (K_pad * 16 bytes), the candidate lists of the single pass (12 bytes a
+ * candidate, K_pad * W / 16384 of them clamped to [2^16, 2^24]), the locally normalised
+ * series and its lag sums (n * 4 + (17 L + 1) * 8 bytes), the predictor's spectrum and,
+ * with an FFT bank, per-block rho^2 partial sums (tiles * K_pad * 8 bytes). */
 bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_t n_segs,
                                    const bf_search_params* params, size_t* bytes);
 
-/* The search of bf_search_batch plus the kappa-sigma tails of every series: the
- * contraction runs twice on the stream (the first pass also sums rho^2 per template, the
- * second extracts the tails against kappa * sigma_k); with an FFT bank the search, the
- * rho^2 sums and the extraction are three passes of the FFT kernel over the data spectra.
- * kappa finite and >= 0; sigma, bin_counts and n_tails are required.  segs is a host
- * array. */
+/* The search of bf_search_batch plus the kappa-sigma tails of every series, in one pass of
+ * the contraction: before it, sigma_k is predicted from the series' own spectrum by
+ * Parseval's theorem (Sec. 2.2: the mean square of template k's output is the sum over
+ * frequency of |H_k|^2 times the power of the locally normalised series); the pass sums the
+ * exact rho^2 per template and keeps every (tau, k) above 0.9 kappa times the prediction.
+ * A check then selects the tails against the exact kappa * sigma_k; a series whose exact
+ * threshold falls below the kept bound, or whose candidate lists overflow, gets a second
+ * pass that extracts its tails directly.  Results are the same bit for bit as with two
+ * passes (sums first, extraction second).  With an FFT bank of N < 8192 points the search,
+ * the sums and the extraction are three passes of the FFT kernel.  kappa finite and >= 0;
+ * sigma, bin_counts and n_tails are required.  segs is a host array. */
 bf_status bf_search_tails(const bf_bank* bank, const bf_tail_segment* segs, int32_t n_segs,
                           float kappa, const bf_search_params* params, void* workspace,
                           size_t workspace_bytes, bf_stream stream);

@@ -23,8 +23,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfly.so")
 
 ARCH = "gfx950"
-SOURCES = ["bfly_kernels.hip", "bfly_fft.hip", "bfly_coinc.hip", "bfly_noalloc.hip", "bfly_api.cpp",
-           "bfly_server.cpp"]
+SOURCES = ["bfly_kernels.hip", "bfly_fft.hip", "bfly_tails.hip", "bfly_coinc.hip",
+           "bfly_noalloc.hip", "bfly_api.cpp", "bfly_server.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     "-ffp-contract=off",

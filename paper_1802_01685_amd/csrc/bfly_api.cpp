@@ -208,6 +208,26 @@ void release_staging(Staging* s, bool recorded) {
 
 int g_slots = 0;  // concurrent work-groups of the contraction kernel (one per CU)
 
+// Environment knobs, read at every call (so a test can switch them between calls).
+bool env_flag(const char* name) {
+  const char* e = getenv(name);
+  return e && e[0] == '1';
+}
+int64_t env_int(const char* name, int64_t dflt) {
+  const char* e = getenv(name);
+  if (!e || !*e) return dflt;
+  char* end = nullptr;
+  const long long v = strtoll(e, &end, 10);
+  return (end && *end == 0) ? (int64_t)v : dflt;
+}
+double env_double(const char* name, double dflt) {
+  const char* e = getenv(name);
+  if (!e || !*e) return dflt;
+  char* end = nullptr;
+  const double v = strtod(e, &end);
+  return (end && *end == 0 && std::isfinite(v) && v > 0.0) ? v : dflt;
+}
+
 // Tile shape of the contraction kernel: tm template blocks x tn offset blocks (of 32) per
 // wave, and the K-loop schedule.  BF_TILE=<tm>x<tn>[i|p] (e.g. "2x8i"; i = interleaved,
 // p = pair streaming) overrides the default -- a tuning knob for experiments; FP32 and BF16 results do not
@@ -305,9 +325,16 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     }
   }
 
-  // the FFT form's search pass is a plain search; its sigma pass comes after
-  const SearchDev sp = make_search(b, prm, with_tails && b.precision != P_FFT ? MODE_SIGMA
-                                                                           : MODE_SEARCH, kappa);
+  // A tail search runs in one pass unless BF_TAILS_TWO_PASS=1 (a comparison knob; the
+  // results are the same bit for bit) or the FFT form's kernel lacks the single-pass mode
+  // (N < 8192).  In two passes the FFT form's search pass is a plain search and its sigma
+  // pass comes after.
+  const bool onepass = with_tails && !env_flag("BF_TAILS_TWO_PASS") &&
+                       (b.precision != P_FFT || fft_onepass_available(b));
+  const int pass_mode = !with_tails ? MODE_SEARCH
+                        : b.precision == P_FFT ? (onepass ? MODE_ONEPASS : MODE_SEARCH)
+                                               : MODE_SIGMA;
+  const SearchDev sp = make_search(b, prm, pass_mode, kappa);
   SeriesBufs one;                 // a single series needs no host allocation
   std::vector<SeriesBufs> many;
   if (n_segs > 1) many.resize((size_t)n_segs);
@@ -322,6 +349,12 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
     q.n = segs[i].n;
     q.out = segs[i].out;
     if (with_tails) q.tails = &tails[i];
+    q.onepass = onepass;
+    if (onepass) {
+      // BF_TAILS_CAND_CAP lowers the candidate room (a knob that forces the checked path)
+      const int64_t cap = env_int("BF_TAILS_CAND_CAP", q.cand_cap);
+      if (cap >= 0 && cap < q.cand_cap) q.cand_cap = cap;
+    }
   }
   int slots = 0;
   if ((st = device_slots(&slots)) != BF_OK) return st;
@@ -359,6 +392,13 @@ bf_status run_batch(const bf_bank* bank, const bf_segment* segs, int32_t n_segs,
   SearchDev sp_t = sp;
   sp_t.mode = MODE_TAILS;
   if (b.precision != P_FFT) HIP_TRY(prepare_main(b, sp_t), "hipFuncSetAttribute(k_main)");
+  if (onepass) {
+    // BF_TAILS_MARGIN overrides the predicted-threshold margin (a knob; above 1 it makes the
+    // check fail, which exercises the fallback)
+    const float margin = (float)env_double("BF_TAILS_MARGIN", TAILS_MARGIN);
+    return enqueue_onepass_tail_kernels(bank, sp, sp_t, tab_dev, n_segs, xb, ti.n_items,
+                                        margin, stream, te);
+  }
   return enqueue_tail_kernels(b, sp, sp_t, tab_dev, n_segs, xb, ti.n_items, stream, te);
 }
 
@@ -374,9 +414,27 @@ size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails) {
     off = align256(off + (size_t)b.K_pad * sizeof(unsigned long long));
     off = align256(off + sizeof(unsigned long long));
     off = align256(off + (size_t)b.K_pad * sizeof(float));
+    // single-pass area: thr_lo, n_cand + redo, candidates, zloc, lag sums, Q
+    const size_t cap = (size_t)cand_capacity(b, W);
+    off = align256(off + (size_t)b.K_pad * sizeof(float));
+    off = align256(off + (CAND_SHARDS + 1) * sizeof(unsigned long long));
+    off = align256(off + cap * 4);
+    off = align256(off + cap * 4);
+    off = align256(off + cap * 4);
+    off = align256(off + (size_t)n * sizeof(float));
+    off = align256(off + (size_t)ACF_CHUNKS * b.L * sizeof(double));
+    off = align256(off + (size_t)(b.L + 1) * sizeof(double));
+    off = align256(off + (size_t)(pred_points(b) / 2 + 1) * sizeof(float));
+    if (b.precision == P_FFT && b.fft_m == 4096)
+      off = align256(off + (size_t)fft_blocks(b, W) * b.K_pad * sizeof(unsigned long long));
   }
   if (b.precision == P_FFT) off = align256(off + fft_blocks(b, W) * (size_t)(b.fft_m + 2) * 8);
   return off;
+}
+
+int64_t cand_capacity(const BankDev& b, int64_t W) {
+  const int64_t c = b.K_pad * W / 16384;
+  return c < 65536 ? 65536 : (c > ((int64_t)1 << 24) ? ((int64_t)1 << 24) : c);
 }
 
 void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s, bool tails) {
@@ -399,6 +457,32 @@ void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s, boo
     off = align256(off + sizeof(unsigned long long));
     s->thr = (float*)(base + off);
     off = align256(off + (size_t)b.K_pad * sizeof(float));
+    const int64_t cap = cand_capacity(b, W);
+    s->thr_lo = (float*)(base + off);
+    off = align256(off + (size_t)b.K_pad * sizeof(float));
+    s->n_cand = (unsigned long long*)(base + off);
+    s->redo = (uint32_t*)(base + off + CAND_SHARDS * sizeof(unsigned long long));
+    off = align256(off + (CAND_SHARDS + 1) * sizeof(unsigned long long));
+    s->c_tau = (int32_t*)(base + off);
+    off = align256(off + (size_t)cap * 4);
+    s->c_k = (int32_t*)(base + off);
+    off = align256(off + (size_t)cap * 4);
+    s->c_rho = (float*)(base + off);
+    off = align256(off + (size_t)cap * 4);
+    s->cand_cap = cap;
+    s->zloc = (float*)(base + off);
+    off = align256(off + (size_t)n * sizeof(float));
+    s->acf_part = (double*)(base + off);
+    off = align256(off + (size_t)ACF_CHUNKS * b.L * sizeof(double));
+    s->acf = (double*)(base + off);
+    off = align256(off + (size_t)(b.L + 1) * sizeof(double));
+    s->qspec = (float*)(base + off);
+    off = align256(off + (size_t)(pred_points(b) / 2 + 1) * sizeof(float));
+    s->sig_part = nullptr;
+    if (b.precision == P_FFT && b.fft_m == 4096) {
+      s->sig_part = (unsigned long long*)(base + off);
+      off = align256(off + (size_t)fft_blocks(b, W) * b.K_pad * sizeof(unsigned long long));
+    }
   }
   s->xspec = nullptr;
   if (b.precision == P_FFT) s->xspec = (float2*)(base + off);
@@ -542,6 +626,8 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
     d.xspec = s[i].xspec;
     const bf_tails* t = s[i].tails;
     d.sig_acc = t ? s[i].sig_acc : nullptr;
+    // per-block sums only where the kernel that writes them runs (k_fft4k)
+    d.sig_part = (t && b.precision == P_FFT && fft_onepass_available(b)) ? s[i].sig_part : nullptr;
     d.n_ok = t ? s[i].n_ok : nullptr;
     d.thr = t ? s[i].thr : nullptr;
     d.sigma = t ? t->sigma : nullptr;
@@ -551,6 +637,18 @@ TableInfo fill_table(const BankDev& b, const SearchDev& sp, const SeriesBufs* s,
     d.t_bins = t ? t->bin_counts : nullptr;
     d.n_tails = t ? (unsigned long long*)t->n_tails : nullptr;
     d.tail_cap = t ? t->capacity : 0;
+    const bool one = t && s[i].onepass;
+    d.thr_lo = one ? s[i].thr_lo : nullptr;
+    d.c_tau = one ? s[i].c_tau : nullptr;
+    d.c_k = one ? s[i].c_k : nullptr;
+    d.c_rho = one ? s[i].c_rho : nullptr;
+    d.n_cand = one ? s[i].n_cand : nullptr;
+    d.cand_cap = one ? s[i].cand_cap : 0;
+    d.redo = one ? s[i].redo : nullptr;
+    d.zloc = one ? s[i].zloc : nullptr;
+    d.acf_part = one ? s[i].acf_part : nullptr;
+    d.acf = one ? s[i].acf : nullptr;
+    d.qspec = one ? s[i].qspec : nullptr;
     ti.max_W = std::max(ti.max_W, d.W);
     ti.max_words = std::max(ti.max_words, std::max(d.W, d.spec ? d.spec_rows * b.n_bins : 0));
   }
@@ -629,6 +727,42 @@ bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
   }
   HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
   HIP_TRY(launch_main(table_dev, main_blocks, b, sp_tails, stream), "k_main launch");
+  return BF_OK;
+}
+
+bf_status enqueue_onepass_tail_kernels(const bf_bank* bank, const SearchDev& sp_pass,
+                                       const SearchDev& sp_tails, const BatchHdr* table_dev,
+                                       int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                                       float margin, hipStream_t stream, TimingSet* te) {
+  const BankDev& b = bank->dev;
+  const int32_t xb = x_blocks > 0 ? x_blocks : 1;
+  if (te) HIP_TRY(hipEventRecord(te->ev[0], stream), "hipEventRecord");
+  HIP_TRY(launch_zero(table_dev, seg_slots, xb, b, sp_pass, stream), "k_zero launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[1], stream), "hipEventRecord");
+  HIP_TRY(launch_prefix(table_dev, seg_slots, stream), "k_prefix launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[2], stream), "hipEventRecord");
+  HIP_TRY(launch_norms(table_dev, seg_slots, xb, b.L, sp_pass.norm, stream), "k_norms launch");
+  // the predictor
+  HIP_TRY(launch_acf(table_dev, seg_slots, b.L, stream), "k_acf launch");
+  HIP_TRY(launch_qspec(table_dev, seg_slots, b.L, pred_points(b), stream), "k_qspec launch");
+  HIP_TRY(launch_pred(table_dev, seg_slots, bank->grid, b, sp_tails.kappa, margin, stream),
+          "k_pred launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[3], stream), "hipEventRecord");
+  if (b.precision == P_FFT)
+    HIP_TRY(launch_fft_search(table_dev, main_blocks, b, sp_pass, stream), "k_fft launch");
+  else
+    HIP_TRY(launch_main(table_dev, main_blocks, b, sp_pass, stream), "k_main launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[4], stream), "hipEventRecord");
+  HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp_pass, stream), "k_finalize launch");
+  HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
+  HIP_TRY(launch_tails_check(table_dev, seg_slots, b, stream), "k_tails_check launch");
+  HIP_TRY(launch_tails_keep(table_dev, seg_slots, b, stream), "k_tails_keep launch");
+  // the tails pass: every work item of a series whose check passed returns at once
+  if (b.precision == P_FFT)
+    HIP_TRY(launch_fft_pass(table_dev, main_blocks, b, sp_tails, stream), "k_fft tails launch");
+  else
+    HIP_TRY(launch_main(table_dev, main_blocks, b, sp_tails, stream), "k_main launch");
+  if (te) HIP_TRY(hipEventRecord(te->ev[5], stream), "hipEventRecord");
   return BF_OK;
 }
 

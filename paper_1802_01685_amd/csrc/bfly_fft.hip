@@ -315,6 +315,125 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_bank(GridDev g, BankDev b,
   rfft_post<M>(buf, spectra + k * (int64_t)(M + 2));
 }
 
+// ---- single-pass tail search: predicted lower thresholds ---------------------------------
+// thr_lo[k] = kappa * margin * sqrt(P_k / (n_ok N)), P_k = sum over f in [0, N) of
+// |H_k(f)|^2 Q(f) (Q from k_qspec, real and even: the bins 1 .. N/2 - 1 count twice), or +inf
+// past the bank's templates and for a series without a non-degenerate offset.
+constexpr int PRED_SERIES = 8;   // series per sweep of a template's spectrum
+
+__device__ __forceinline__ void pred_store(const SegDesc& sg, int64_t k, const BankDev& b,
+                                           double P, int N, float kappa, float margin) {
+  const double nok = sg.acf[b.L];
+  float v = __builtin_inff();
+  if (k < b.K && nok > 0.0) v = (float)((double)kappa * (double)margin * sqrt(P / (nok * (double)N)));
+  sg.thr_lo[k] = v;
+}
+
+// The FFT form: the spectra are the bank's (N = 2M); one wave per template, every series.
+__global__ __launch_bounds__(256) void k_pred_bank(const BatchHdr* __restrict__ hdr, BankDev b,
+                                                   float kappa, float margin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= b.K_pad) return;
+  const int M = b.fft_m, N = 2 * b.fft_m;
+  const float2* hk = (const float2*)b.data + k * (int64_t)(M + 2);
+  const SegDesc* segs = hdr_segs(hdr);
+  for (int s0 = 0; s0 < hdr->n_segs; s0 += PRED_SERIES) {
+    double P[PRED_SERIES];
+#pragma unroll
+    for (int i = 0; i < PRED_SERIES; ++i) P[i] = 0.0;
+    for (int f = lane; f <= M; f += 64) {
+      const float2 h = k < b.K ? hk[f] : make_float2(0.0f, 0.0f);
+      const double w = (f == 0 || f == M) ? 1.0 : 2.0;
+      const double h2 = w * ((double)h.x * h.x + (double)h.y * h.y);
+#pragma unroll
+      for (int i = 0; i < PRED_SERIES; ++i)
+        if (s0 + i < hdr->n_segs && segs[s0 + i].qspec) P[i] += h2 * (double)segs[s0 + i].qspec[f];
+    }
+#pragma unroll
+    for (int i = 0; i < PRED_SERIES; ++i) {
+      double v = P[i];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0 && s0 + i < hdr->n_segs && segs[s0 + i].thr_lo)
+        pred_store(segs[s0 + i], k, b, v, N, kappa, margin);
+    }
+  }
+}
+
+// The direct forms: one work-group per template builds it as the FFT bank does (float64,
+// rounded to float32), transforms it on N = 2M points, and sums |H|^2 Q for every series.
+template <int M>
+__global__ __launch_bounds__(Plan<M>::T) void k_pred_gen(const BatchHdr* __restrict__ hdr,
+                                                         GridDev g, BankDev b, float kappa,
+                                                         float margin) {
+  constexpr int T = Plan<M>::T;
+  __shared__ float2 buf[Padded<M>::n];
+  __shared__ double red[T / 64];
+  const int64_t k = blockIdx.x;
+  const bool real = k < b.K;
+  double f0 = 0.0, fdot = 0.0, mu = 0.0, nrm = 1.0;
+  if (real) {
+    const int64_t il = k / g.n_fdot;
+    const int j = (int)(k % g.n_fdot);
+    const int64_t ig = g.f0_lo + il;
+    f0 = (g.n_f0 > 1 && ig == g.n_f0 - 1) ? g.f0_max : (double)ig * g.f0_step + g.f0_min;
+    fdot = (g.n_fdot > 1 && j == g.n_fdot - 1) ? g.fdot_max
+                                               : (double)j * g.fdot_step + g.fdot_min;
+    double s1 = 0.0;
+    for (int n = threadIdx.x; n < b.L; n += T) s1 += template_sample(g.fs, f0, fdot, n);
+    mu = block_sum_d<T / 64>(s1, red) / (double)b.L;
+    double s2 = 0.0;
+    for (int n = threadIdx.x; n < b.L; n += T) {
+      const double v = template_sample(g.fs, f0, fdot, n) - mu;
+      s2 += v * v;
+    }
+    s2 = block_sum_d<T / 64>(s2, red);
+    nrm = s2 > 0.0 ? sqrt(s2) : 1.0;
+  }
+  // taps past 2M alias onto the transform (only when L > 2M; a prediction, checked later)
+  for (int n = threadIdx.x; n < M; n += T) {
+    float2 z = make_float2(0.0f, 0.0f);
+    for (int q = 2 * n; q < b.L && real; q += 2 * M) {
+      z.x += (float)((template_sample(g.fs, f0, fdot, q) - mu) / nrm);
+      if (q + 1 < b.L) z.y += (float)((template_sample(g.fs, f0, fdot, q + 1) - mu) / nrm);
+    }
+    buf[pad(n)] = z;
+  }
+  __syncthreads();
+  float2 out[8];
+  PassTw<M, false> tw;
+  tw.init();
+  fft_run<M, false, false>(buf, tw, out);
+  const SegDesc* segs = hdr_segs(hdr);
+  for (int s0 = 0; s0 < hdr->n_segs; s0 += PRED_SERIES) {
+    double P[PRED_SERIES];
+#pragma unroll
+    for (int i = 0; i < PRED_SERIES; ++i) P[i] = 0.0;
+    for (int kk = threadIdx.x; kk <= M; kk += T) {
+      // X[kk] from the complex transform (the post-processing of rfft_post)
+      const float2 zk = buf[pad(kk & (M - 1))];
+      const float2 zc = cconj(buf[pad((M - kk) & (M - 1))]);
+      const float2 e = cscale(cadd(zk, zc), 0.5f);
+      const float2 d = cscale(csub(zk, zc), 0.5f);
+      const float2 o = make_float2(d.y, -d.x);
+      const float2 w = cis_rev<false>((float)kk / (float)(2 * M));
+      const float2 X = cadd(e, cmul(w, o));
+      const double wt = (kk == 0 || kk == M) ? 1.0 : 2.0;
+      const double h2 = wt * ((double)X.x * X.x + (double)X.y * X.y);
+#pragma unroll
+      for (int i = 0; i < PRED_SERIES; ++i)
+        if (s0 + i < hdr->n_segs && segs[s0 + i].qspec) P[i] += h2 * (double)segs[s0 + i].qspec[kk];
+    }
+#pragma unroll
+    for (int i = 0; i < PRED_SERIES; ++i) {
+      const double v = block_sum_d<T / 64>(P[i], red);
+      if (threadIdx.x == 0 && s0 + i < hdr->n_segs && segs[s0 + i].thr_lo)
+        pred_store(segs[s0 + i], k, b, v, 2 * M, kappa, margin);
+    }
+  }
+}
+
 // Data spectra: one work-group per (series, block) tile, persistent over the batch's tiles.
 template <int M>
 __global__ __launch_bounds__(Plan<M>::T) void k_fft_data(const BatchHdr* __restrict__ hdr,
@@ -437,6 +556,7 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
       if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
     }
     const SegDesc& sg = segs[lo];
+    if (MODE == MODE_TAILS && sg.redo && sg.redo[0] == 0u) continue;   // see k_fft4k
     const int64_t blk = tt - sg.tile0;
     const int tau_base = (int)(blk * valid);     // series are shorter than 2^31 samples
     const int b_lo = (int)((int64_t)rg * b.n_bins / n_ranges);
@@ -679,7 +799,7 @@ __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* 
 }
 
 template <int SMAX, int MODE>
-__global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
+__global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
                                                   SearchDev p) {
   using namespace fft4k;
   static_assert(SMAX >= 1 && SMAX <= 16, "output slots");
@@ -691,6 +811,9 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
   // j mod NS = m: entry [(r - 1) NS + m] (lanes read consecutive entries)
   __shared__ float2 tab2[7 * 8];
   __shared__ float2 tab3[7 * 64];
+  // sigma and single-pass modes: each wave's fixed-point sum of rho^2 for the last two
+  // templates (by parity); thread 0 adds the four after the next barrier and stores it
+  __shared__ unsigned long long sig_slot[2][4];
   const SegDesc* segs = hdr_segs(hdr);
   const float2* spectra = (const float2*)b.data;
   const int n_ranges = hdr->n_ranges;
@@ -702,9 +825,15 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
 
   // first-pass butterflies j0 = t and j1 = 512 - t (thread 0: 0, and 256 handed over);
   // pair r = (a_r, M - a_r) with a_r = t + 512 r; its post-processing twiddle
-  float2 wpair[8];
+  // LEAN forms the pair twiddles and pass 4's twiddle powers per template instead of keeping
+  // them in registers (for builds short of registers; off in every mode compiled now).
+  constexpr bool LEAN = false;
+  const float2 wt = cis_rev<true>((float)t / (float)(2 * M));   // wpair[r] = wt exp(2 pi i r/16)
+  float2 wpair[LEAN ? 1 : 8];
+  if constexpr (!LEAN) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) wpair[r] = cis_rev<true>((float)(t + 512 * r) / (float)(2 * M));
+    for (int r = 0; r < 8; ++r) wpair[r] = cis_rev<true>((float)(t + 512 * r) / (float)(2 * M));
+  }
   // lanes 0..3 of wave 0: pair (256 + 512 t, M - 256 - 512 t) of butterfly 256
   const bool helper = t < 4;
   const int ha_idx = 256 + 512 * (t & 3);
@@ -720,11 +849,16 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       tab2[i] = cis_rev<true>((float)((m2 * r2) & 63) / 64.0f);
     }
   }
-  float2 tw4a[7], tw4b[7];
+  float2 tw4a[LEAN ? 1 : 7], tw4b[LEAN ? 1 : 7];
+  if constexpr (LEAN) {
+    tw4a[0] = cis_rev<true>((float)t / 4096.0f);
+    tw4b[0] = cis_rev<true>((float)(t + 256) / 4096.0f);
+  } else {
 #pragma unroll
-  for (int r = 1; r < 8; ++r) {
-    tw4a[r - 1] = cis_rev<true>((float)((t * r) & 4095) / 4096.0f);
-    tw4b[r - 1] = cis_rev<true>((float)(((t + 256) * r) & 4095) / 4096.0f);
+    for (int r = 1; r < 8; ++r) {
+      tw4a[r - 1] = cis_rev<true>((float)((t * r) & 4095) / 4096.0f);
+      tw4b[r - 1] = cis_rev<true>((float)(((t + 256) * r) & 4095) / 4096.0f);
+    }
   }
   __syncthreads();
 
@@ -750,6 +884,8 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
     }
     const SegDesc& sg = segs[lo];
+    // after a single-pass search the tails pass runs only for series whose prediction failed
+    if (MODE == MODE_TAILS && sg.redo && sg.redo[0] == 0u) continue;
     const int64_t blk = tt - sg.tile0;
     const int tau_base = (int)(blk * valid);     // series are shorter than 2^31 samples
     const int b_lo = (int)((int64_t)rg * b.n_bins / n_ranges);
@@ -776,13 +912,14 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
     const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
     float binmax[NO];
     int binarg[NO];
-    float inv[NO];
+    float inv[NO];     // sigma, tails and single-pass modes: 1/sqrt(E) as float (0 if invalid)
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-      if constexpr (MODE == MODE_SEARCH) {
+      if constexpr (MODE == MODE_SEARCH || MODE == MODE_ONEPASS) {
         binmax[o] = -1.0f;
         binarg[o] = -1;
-      } else {
+      }
+      if constexpr (MODE != MODE_SEARCH) {
         const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
         inv[o] = pos < pos_end ? (float)sg.inv_norm[tau_base + pos] : 0.0f;
       }
@@ -811,7 +948,8 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       float2 v0[8], v1[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r)
-        mirror_pair(ha[r], xa[r], hb[r], xb[r], wpair[r], v0[r], v1[7 - r]);
+        mirror_pair(ha[r], xa[r], hb[r], xb[r],
+                    LEAN ? twiddle16_q<true>(wt, r) : wpair[LEAN ? 0 : r], v0[r], v1[7 - r]);
       if (helper) {
         float2 ya, yb;
         mirror_pair(hha, hand_x[2 * t], hhb, hand_x[2 * t + 1], whelp, ya, yb);
@@ -835,6 +973,13 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         w1[r] = v1[r];
       }
       __syncthreads();
+      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
+        if (t == 0 && k > k_lo && sg.sig_part) {
+          const int q = (k - 1) & 1;
+          sg.sig_part[blk * b.K_pad + (k - 1)] =
+              ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
+        }
+      }
       float2 y0[8], y1[8];
       {
         float2 w[7];
@@ -850,7 +995,20 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
       }
       __syncthreads();
-      pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+      if constexpr (LEAN) {
+        // pass 4's twiddle powers as running products of the bases
+        float2 wa[7], wb[7];
+        wa[0] = tw4a[0];
+        wb[0] = tw4b[0];
+#pragma unroll
+        for (int r = 1; r < 7; ++r) {
+          wa[r] = cmul(wa[r - 1], tw4a[0]);
+          wb[r] = cmul(wb[r - 1], tw4b[0]);
+        }
+        pass8x2<512, true>(bufp, bufq, wa, wb, y0, y1);
+      } else {
+        pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+      }
       {
         float2* s = bufp;
         bufp = bufq;
@@ -862,12 +1020,17 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         const float2 c = (s & 1) ? y1[s >> 1] : y0[s >> 1];
         return (o & 1) ? c.y : c.x;
       };
-      if constexpr (MODE == MODE_SIGMA) {
+      // rho = f32(d / sqrt(E)): (y scale) is exact and the product of two floats is exact in
+      // float64, so one float32 multiply rounds it exactly as the float64 route would
+      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
         float q = 0.0f;
+        bool any = false;
+        [[maybe_unused]] const float tlo = MODE == MODE_ONEPASS ? sg.thr_lo[k] : 0.0f;
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
-          const float rr = (float)((double)(outv(o) * scale) * (double)inv[o]);
+          const float rr = (outv(o) * scale) * inv[o];
           q = fmaf(rr, rr, q);
+          if constexpr (MODE == MODE_ONEPASS) any = any || fabsf(rr) > tlo;
         }
         unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
 #pragma unroll
@@ -876,14 +1039,37 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
           const unsigned fhi = __shfl_xor((unsigned)(f >> 32), o, 64);
           f += ((unsigned long long)fhi << 32) | flo;
         }
-        if ((t & 63) == 0 && f != 0ull) atomicAdd(sg.sig_acc + k, f);
-        continue;
+        if ((t & 63) == 0) {
+          if (sg.sig_part)
+            sig_slot[k & 1][t >> 6] = f;
+          else if (f != 0ull)
+            atomicAdd(sg.sig_acc + k, f);
+        }
+        if constexpr (MODE == MODE_SIGMA) continue;
+        if (any) {
+          // candidates above the predicted threshold (rare): appended with one atomic each
+#pragma unroll
+          for (int o = 0; o < NO; ++o) {
+            const float rr = (outv(o) * scale) * inv[o];
+            if (fabsf(rr) > tlo) {
+              const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
+              const int64_t per = sg.cand_cap / CAND_SHARDS;
+              const unsigned long long slot = atomicAdd(sg.n_cand + shard, 1ull);
+              if ((int64_t)slot < per) {
+                const int64_t at = shard * per + (int64_t)slot;
+                sg.c_tau[at] = tau_base + 2 * t + 512 * (o >> 1) + (o & 1);
+                sg.c_k[at] = k;
+                sg.c_rho[at] = rr;
+              }
+            }
+          }
+        }
       }
       if constexpr (MODE == MODE_TAILS) {
         const float thr = sg.thr[k];
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
-          const float rf = (float)((double)(outv(o) * scale) * (double)inv[o]);
+          const float rf = (outv(o) * scale) * inv[o];
           if (fabsf(rf) > thr) {
             const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
             if ((int64_t)slot < sg.tail_cap) {
@@ -944,6 +1130,15 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         left = nfd;
       }
     }
+    if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
+      // the item's last template
+      __syncthreads();
+      if (t == 0 && k_hi > k_lo && sg.sig_part) {
+        const int q = (k_hi - 1) & 1;
+        sg.sig_part[blk * b.K_pad + (k_hi - 1)] =
+            ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
+      }
+    }
   }
 }
 
@@ -962,6 +1157,12 @@ bool fft4k_enabled() {
   }();
   return on;
 }
+
+}  // namespace
+
+bool fft_onepass_available(const BankDev& b) { return b.fft_m == 4096 && fft4k_enabled(); }
+
+namespace {
 
 template <int MODE>
 hipError_t launch_fft4k(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
@@ -1004,7 +1205,11 @@ hipError_t launch_fft_search_t(const BatchHdr* hdr, int64_t blocks, const BankDe
   hipLaunchKernelGGL(k_fft_data<M>, dim3((unsigned)blocks), dim3(Plan<M>::T), 0, s, hdr, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (M == 4096 && fft4k_enabled()) return launch_fft4k<MODE_SEARCH>(hdr, blocks, b, p, s);
+  if (M == 4096 && fft4k_enabled()) {
+    if (p.mode == MODE_ONEPASS) return launch_fft4k<MODE_ONEPASS>(hdr, blocks, b, p, s);
+    return launch_fft4k<MODE_SEARCH>(hdr, blocks, b, p, s);
+  }
+  if (p.mode != MODE_SEARCH) return hipErrorInvalidValue;
   if (fft_occupancy() == 4)
     hipLaunchKernelGGL((k_fft_main<M, 4, MODE_SEARCH>), dim3((unsigned)blocks),
                        dim3(Plan<M>::T), 0, s, hdr, b, p);
@@ -1064,6 +1269,32 @@ hipError_t launch_fft_pass(const BatchHdr* hdr, int64_t blocks, const BankDev& b
                            const SearchDev& p, hipStream_t s) {
   if (blocks < 1) return hipSuccess;
   BFLY_FFT_DISPATCH(launch_fft_pass_t, hdr, blocks, b, p, s);
+}
+
+hipError_t launch_pred(const BatchHdr* hdr, int32_t seg_slots, const GridDev& g,
+                       const BankDev& b, float kappa, float margin, hipStream_t s) {
+  (void)seg_slots;
+  if (b.precision == P_FFT) {
+    hipLaunchKernelGGL(k_pred_bank, dim3((unsigned)((b.K_pad + 3) / 4)), dim3(256), 0, s, hdr,
+                       b, kappa, margin);
+    return hipGetLastError();
+  }
+  const unsigned blocks = (unsigned)b.K_pad;
+  switch (pred_points(b) / 2) {
+    case 512:
+      hipLaunchKernelGGL(k_pred_gen<512>, dim3(blocks), dim3(Plan<512>::T), 0, s, hdr, g, b, kappa, margin);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(k_pred_gen<1024>, dim3(blocks), dim3(Plan<1024>::T), 0, s, hdr, g, b, kappa, margin);
+      break;
+    case 2048:
+      hipLaunchKernelGGL(k_pred_gen<2048>, dim3(blocks), dim3(Plan<2048>::T), 0, s, hdr, g, b, kappa, margin);
+      break;
+    default:
+      hipLaunchKernelGGL(k_pred_gen<4096>, dim3(blocks), dim3(Plan<4096>::T), 0, s, hdr, g, b, kappa, margin);
+      break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace bfly

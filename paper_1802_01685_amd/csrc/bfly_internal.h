@@ -91,6 +91,9 @@ struct SegDesc {
   float2* xspec;        // FFT form: [n_tiles][M + 2] spectra of the data blocks
   // kappa-sigma tails (null unless the search extracts them)
   unsigned long long* sig_acc;   // [K_pad] fixed-point sums of rho^2 per template
+  unsigned long long* sig_part;  // FFT form at N = 8192: [n_tiles][K_pad] the same sums per
+                                 // block (one plain store per work item and template, no
+                                 // atomics contending across work-groups; summed by k_sigma)
   unsigned long long* n_ok;      // [1] non-degenerate offsets
   float* thr;                    // [K_pad] kappa * sigma_k (+inf past K)
   float* sigma;                  // [K] output sigma_k
@@ -100,7 +103,25 @@ struct SegDesc {
   uint32_t* t_bins;              // [n_bins] tails per f0 bin
   unsigned long long* n_tails;   // [1] tails found
   int64_t tail_cap;
+  // single-pass tail search (null when the tails are extracted by a second pass): the
+  // predicted lower thresholds, the candidates above them and the check of the prediction
+  float* thr_lo;                 // [K_pad] kappa * margin * predicted sigma_k (+inf past K)
+  int32_t* c_tau;                // [cand_cap] candidate offsets
+  int32_t* c_k;                  // [cand_cap] candidate local template indices
+  float* c_rho;                  // [cand_cap] candidate rho (signed)
+  unsigned long long* n_cand;    // [CAND_SHARDS] candidates found per shard
+  int64_t cand_cap;              // CAND_SHARDS shards of cand_cap / CAND_SHARDS entries
+  uint32_t* redo;                // [1] 1: the prediction did not hold, run the tails pass
+  float* zloc;                   // [n] the locally normalised series
+  double* acf_part;              // [ACF_CHUNKS][L] lag sums over chunks of the series
+  double* acf;                   // [L + 1] lag sums, then the non-degenerate offset count
+  float* qspec;                  // [pred_n / 2 + 1] their cosine transform
 };
+constexpr int ACF_CHUNKS = 16;
+// Candidates are appended to one of CAND_SHARDS sub-lists (by work-group), each with its own
+// counter: appends to one global counter from every work-group contend (device-scope atomics
+// on one address serialise across the XCDs).
+constexpr int CAND_SHARDS = 256;
 
 // The level subtracted from every staged sample: the mean of the series over its finite
 // samples, from its prefix sums, rounded to a multiple of q = 2^floor(log2 sigma), sigma the
@@ -177,7 +198,11 @@ struct SearchDev {
 
 // Contraction passes: the search; the search that also sums rho^2 per template; the pass
 // that extracts the tails above kappa * sigma_k (and does nothing else).
-enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2 };
+enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2, MODE_ONEPASS = 3 };
+
+// Single-pass tail search: the fraction of the predicted sigma below which candidates are
+// kept (the prediction is checked against the exact sigma after the pass).
+constexpr float TAILS_MARGIN = 0.9f;
 
 // Bytes of the quantised templates, of the per-template side tables, and of the whole bank
 // allocation (templates, side tables, then a 256-byte status word).
@@ -223,6 +248,26 @@ hipError_t launch_fft_bank(const GridDev& g, const BankDev& b, void* dst, hipStr
 hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                              const SearchDev& p, hipStream_t s);
 // The sigma or tails pass of a tail search (p.mode), after the search left the data spectra.
+// Single-pass tail search (bfly_tails.hip, bfly_fft.hip).  The predictor: lag sums of each
+// series' locally normalised samples (k_acf), their cosine transform on pred_n points
+// (k_qspec), and per template kappa * margin * sqrt(sum_f |H_k(f)|^2 Q(f) / (n_ok pred_n))
+// from the bank's spectra (FFT form) or from spectra made on the fly (direct forms).  After
+// the pass that sums rho^2 and keeps candidates above those thresholds: k_tails_check flags
+// a series whose exact thresholds fall below the predicted ones (or whose candidates
+// overflowed), and k_tails_keep moves the candidates above the exact thresholds into the
+// tail lists of every series not flagged; the tails pass then runs only for flagged series.
+int pred_points(const BankDev& b);
+// The FFT form's search kernel has the single-pass mode (N = 8192).
+bool fft_onepass_available(const BankDev& b);
+hipError_t launch_acf(const BatchHdr* hdr, int32_t seg_slots, int L, hipStream_t s);
+hipError_t launch_qspec(const BatchHdr* hdr, int32_t seg_slots, int L, int pred_n,
+                        hipStream_t s);
+hipError_t launch_pred(const BatchHdr* hdr, int32_t seg_slots, const GridDev& g,
+                       const BankDev& b, float kappa, float margin, hipStream_t s);
+hipError_t launch_tails_check(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                              hipStream_t s);
+hipError_t launch_tails_keep(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                             hipStream_t s);
 hipError_t launch_fft_pass(const BatchHdr* hdr, int64_t blocks, const BankDev& b,
                            const SearchDev& p, hipStream_t s);
 

@@ -302,7 +302,10 @@ __global__ __launch_bounds__(256) void k_zero(const BatchHdr* __restrict__ hdr, 
     if (t0 == 0) {
       sg.n_ok[0] = 0ull;
       sg.n_tails[0] = 0ull;
+      if (sg.redo) sg.redo[0] = 0u;
     }
+    if (sg.n_cand)
+      for (int64_t i = t0; i < CAND_SHARDS; i += stride) sg.n_cand[i] = 0ull;
   }
 }
 
@@ -919,6 +922,8 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     if (segs[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
   }
   const SegDesc& sg = segs[lo];
+  // after a single-pass search the tails pass runs only for series whose prediction failed
+  if (MODE == MODE_TAILS && sg.redo && sg.redo[0] == 0u) return;
   const int64_t tau0 = (tt - sg.tile0) * (32 * NB * WG_WAVES);
   const int b_lo = (int)((int64_t)r * b.n_bins / n_ranges);
   const int b_hi = (int)((int64_t)(r + 1) * b.n_bins / n_ranges);
@@ -1443,6 +1448,38 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
             const float rf = (float)((double)(acc[t][j][v] * dscale) * inv[j]);
             q[16 * t + v] = fmaf(rf, rf, q[16 * t + v]);
           }
+      if (sg.c_tau) {
+        // single-pass tail search: every owned (tau, k) with |rho| above the predicted lower
+        // threshold is kept as a candidate (rows and ownership as in the tails pass)
+        const float* th = sg.thr_lo + kbase + 4 * h;
+        const int qh = r_lo - 4 * h;
+        const unsigned span = (unsigned)(r_hi - r_lo);
+#pragma unroll
+        for (int t = 0; t < MB; ++t)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const float4 t4 = *(const float4*)(th + 32 * t + 8 * g);
+            const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int c = 32 * t + 8 * g + i;
+                const float rf = (float)((double)(acc[t][j][4 * g + i] * dscale) * inv[j]);
+                if (fabsf(rf) > tv[i] && (unsigned)(c - qh) < span) {
+                  const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
+                  const int64_t per = sg.cand_cap / CAND_SHARDS;
+                  const unsigned long long slot = atomicAdd(sg.n_cand + shard, 1ull);
+                  if ((int64_t)slot < per) {
+                    const int64_t at = shard * per + (int64_t)slot;
+                    sg.c_tau[at] = (int32_t)(tau_w0 + 32 * j + n);
+                    sg.c_k[at] = (int32_t)(kbase + c + 4 * h);
+                    sg.c_rho[at] = rf;
+                  }
+                }
+              }
+          }
+      }
 #pragma unroll
       for (int w = 16; w >= 1; w >>= 1) {
         const bool up = (n & w) != 0;
@@ -1664,7 +1701,12 @@ __global__ __launch_bounds__(256) void k_sigma(const BatchHdr* __restrict__ hdr,
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < b.K_pad; k += stride) {
     float thr = __builtin_inff();
     if (k < b.K) {
-      const double sd = nok > 0.0 ? sqrt((double)sg.sig_acc[k] / SIGMA_FIX_SCALE / nok) : 0.0;
+      unsigned long long acc = 0ull;
+      if (sg.sig_part)
+        for (int64_t blk = 0; blk < sg.n_tiles; ++blk) acc += sg.sig_part[blk * b.K_pad + k];
+      else
+        acc = sg.sig_acc[k];
+      const double sd = nok > 0.0 ? sqrt((double)acc / SIGMA_FIX_SCALE / nok) : 0.0;
       if (sg.sigma) sg.sigma[k] = (float)sd;
       if (nok > 0.0) thr = (float)((double)p.kappa * sd);
     }

@@ -37,11 +37,28 @@ struct SeriesBufs {
   bf_result out;
   // tail search only (else null): workspace sums, counts, thresholds, and the outputs
   unsigned long long* sig_acc = nullptr;
+  unsigned long long* sig_part = nullptr;
   unsigned long long* n_ok = nullptr;
   float* thr = nullptr;
   const bf_tails* tails = nullptr;
   float2* xspec = nullptr;     // FFT form: data block spectra (workspace)
+  // single-pass tail search (workspace; used when the search runs in one pass)
+  float* thr_lo = nullptr;
+  int32_t* c_tau = nullptr;
+  int32_t* c_k = nullptr;
+  float* c_rho = nullptr;
+  unsigned long long* n_cand = nullptr;
+  int64_t cand_cap = 0;
+  uint32_t* redo = nullptr;
+  float* zloc = nullptr;
+  double* acf_part = nullptr;
+  double* acf = nullptr;
+  float* qspec = nullptr;
+  bool onepass = false;        // this search extracts its tails in one pass
 };
+
+// Candidates a single-pass tail search keeps room for (per series of W offsets).
+int64_t cand_capacity(const BankDev& b, int64_t W);
 
 // Bytes of one series' workspace part (prefix sums, counts, norms, maxima, spectrum sums;
 // with tails also the per-template rho^2 sums and thresholds).
@@ -111,6 +128,14 @@ bf_status enqueue_kernels(const BankDev& b, const SearchDev& sp, const BatchHdr*
                           hipStream_t stream, TimingSet* te);
 // The tail search: the kernels above with the contraction in MODE_SIGMA, then k_sigma and
 // the MODE_TAILS contraction (sp_sigma and sp_tails differ only in mode).
+// The single-pass tail search: the predictor, one correlation pass that sums rho^2 and keeps
+// candidates (sp_pass: MODE_SIGMA for k_main, MODE_ONEPASS for the FFT form), the exact
+// thresholds, the check and the selection of the tails, and the tails pass for the series
+// whose check failed (its work-groups return at once for the others).
+bf_status enqueue_onepass_tail_kernels(const bf_bank* bank, const SearchDev& sp_pass,
+                                       const SearchDev& sp_tails, const BatchHdr* table_dev,
+                                       int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,
+                                       float margin, hipStream_t stream, TimingSet* te);
 bf_status enqueue_tail_kernels(const BankDev& b, const SearchDev& sp_sigma,
                                const SearchDev& sp_tails, const BatchHdr* table_dev,
                                int32_t seg_slots, int32_t x_blocks, int64_t main_blocks,

@@ -159,6 +159,56 @@ def test_tails_batch_equals_single_and_truncation(bf, prec):
     assert len(got) == cap and got <= set(zip(full["tau"].tolist(), full["k"].tolist()))
 
 
+def _tails_run(bf, bank, xs32, kappa, env, monkeypatch):
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    try:
+        return _search_tails(bf, bank, xs32, kappa, 1 << 18)
+    finally:
+        for k in env:
+            monkeypatch.delenv(k, raising=False)
+
+
+@pytest.mark.parametrize("prec", ["fft", "f16f6", "fp32", "bf16x3", "fp8"])
+def test_single_pass_equals_two_pass(bf, prec, monkeypatch):
+    """Sec. 2.2 predicts sigma before the search (Parseval): the single-pass tail search keeps
+    the pairs above a predicted lower threshold while it sums rho^2 and selects the tails
+    among them afterwards.  Its search outputs, sigma, tails and counts equal the two-pass
+    search's bit for bit -- by default, when its check of the prediction fails (margin above
+    1: every series falls back to the tails pass) and when its candidates overflow."""
+    from synth import chirp_samples
+    p = BankParams(fs=1024.0, L=1024, n_f0=6, n_fdot=10, f0_min=40.0, f0_max=300.0,
+                   fdot_min=-150.0, fdot_max=150.0)         # L = 1024: the FFT form at N = 8192
+    gr = O.grid(p)
+    sig, _ = chirp_samples(30000, p.fs, 7000 / p.fs, gr.f0[23], gr.fdot[23])
+    a = (white_noise(30000, 41) + 0.4 * sig).astype(np.float32)
+    a[20000:20000 + p.L + 9] = 0.5                        # degenerate windows
+    b = (3.0 * white_noise(20011, 42) + 100.0).astype(np.float32)
+    bank = bf.bank_create(p, prec)
+    kappa = 3.5
+    runs = {name: _tails_run(bf, bank, [a, b], kappa, env, monkeypatch)
+            for name, env in (("one", {}), ("two", {"BF_TAILS_TWO_PASS": "1"}),
+                              ("redo", {"BF_TAILS_MARGIN": "4.0"}),
+                              ("overflow", {"BF_TAILS_CAND_CAP": "4"}))}
+    ref_out, ref_t = runs["two"]
+    assert all(t["n"] > 0 for t in ref_t)
+    for name in ("one", "redo", "overflow"):
+        out, t = runs[name]
+        for i in range(2):
+            for key in ref_out[i]:
+                assert np.array_equal(ref_out[i][key].view(np.uint8), out[i][key].view(np.uint8)), \
+                    (name, i, key)
+            for key in ("sigma", "tau", "k", "rho", "counts"):
+                assert np.array_equal(np.asarray(ref_t[i][key]).view(np.uint8),
+                                      np.asarray(t[i][key]).view(np.uint8)), (name, i, key)
+            assert ref_t[i]["n"] == t[i]["n"], (name, i)
+    # and the single-pass tails are right
+    st = check_tails(a.astype(np.float64), p, runs["one"][1][0],
+                     O.sigma_tails(a.astype(np.float64), p, kappa), kappa, TOL[prec],
+                     f"single-pass/{prec}")
+    print(prec, st)
+
+
 def test_tails_kappa_zero_and_all_degenerate(bf):
     """kappa = 0: every non-degenerate pair is a tail.  A constant series: no non-degenerate
     offset, sigma = 0 and no tails."""
