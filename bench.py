@@ -363,7 +363,9 @@ def tails_leg(bf, torch, p, xs, prec, kappa, steps):
     n_tails = [int(t["n_tails"][0]) for t in tails]
     sig = tails[0]["sigma"].cpu().numpy()
     res = {"kappa": kappa, "precision_form": prec, "ms_per_step": wall / steps * 1e3,
-           "correlations_per_s": corr * steps / wall, "passes": 3 if prec == "fft" else 2,
+           "correlations_per_s": corr * steps / wall,
+           "passes": "1 (a second only for a series whose predicted threshold check fails)"
+                     if prec != "fft" or fft_points(p.L) == 4096 else 3,
            "n_tails": n_tails, "sigma_median_x_sqrtL": float(np.median(sig) * np.sqrt(p.L)),
            "series": ["data", "control"][:len(xs)]}
     del bank, outs, tails, ws
@@ -516,6 +518,9 @@ def main() -> int:
         for form in dict.fromkeys([args.precision, "f16f6"]):
             log(f"tails leg: kappa = {args.tails_kappa}, {form}, 1 + 2 runs")
             tails[form] = tails_leg(bf, torch, p, xs, form, args.tails_kappa, 2)
+            plain = main_res if form == args.precision else forms.get(form)
+            if plain is not None:
+                tails[form]["vs_plain_search"] = tails[form]["ms_per_step"] / plain["ms_per_step"]
             log(f"  {tails[form]}")
 
     serving = {}

@@ -248,6 +248,31 @@ __device__ __forceinline__ void rfft_post(float2* buf, float2* __restrict__ dst)
   }
 }
 
+// Sum of a 64-bit integer over the 64 lanes of a wave, in every lane.  Within each row of 16
+// lanes by DPP (swap neighbours, swap pairs, mirror each half row, mirror the row), which
+// leaves every lane of a row holding the row's sum; the four rows are then added from one
+// lane each.  No LDS round trips (a shuffle chain takes six dependent ones).  Integer sums
+// do not depend on the order, so the result equals any other reduction's.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  v += dpp_u64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_u64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_u64<0x141>(v);   // row_half_mirror
+  v += dpp_u64<0x140>(v);   // row_mirror
+  return (lane_u64(v, 15) + lane_u64(v, 31)) + (lane_u64(v, 47) + lane_u64(v, 63));
+}
+
 // One template sample in float64, with the same formula as the direct bank:
 // cos(2 pi frac(f0 t + fdot t^2 / 2)), t = n / fs.
 __device__ __forceinline__ double template_sample(double fs, double f0, double fdot, int n) {
@@ -503,12 +528,7 @@ __device__ __forceinline__ void fft_flush(const SegDesc& sg, const SearchDev& p,
       }
     }
   }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const unsigned lo = __shfl_xor((unsigned)(fix & 0xFFFFFFFFull), o, 64);
-    const unsigned hi = __shfl_xor((unsigned)(fix >> 32), o, 64);
-    fix += ((unsigned long long)hi << 32) | lo;
-  }
+  fix = wave_sum_u64(fix);
   if ((threadIdx.x & 63) == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
 }
 
@@ -639,12 +659,7 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
           q = fmaf(r1, r1, q);
         }
         unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const unsigned lo = __shfl_xor((unsigned)(f & 0xFFFFFFFFull), o, 64);
-          const unsigned hi = __shfl_xor((unsigned)(f >> 32), o, 64);
-          f += ((unsigned long long)hi << 32) | lo;
-        }
+        f = wave_sum_u64(f);
         if ((tid & 63) == 0 && f != 0ull) atomicAdd(sg.sig_acc + k, f);
         continue;
       }
@@ -944,6 +959,9 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
     float2* bufp = lds;            // pass 1 writes here; the buffers swap every template
     float2* bufq = lds + PADN;
     for (int k = k_lo; k < k_hi; ++k) {
+      // the single pass's kept bound of this template, loaded before the transform needs
+      // the scalar data path's waits
+      [[maybe_unused]] const float tlo = MODE == MODE_ONEPASS ? sg.thr_lo[k] : 0.0f;
       // ---- spectrum product, post-processing and the first radix-8 pass, in registers
       float2 v0[8], v1[8];
 #pragma unroll
@@ -973,19 +991,21 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
         w1[r] = v1[r];
       }
       __syncthreads();
-      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
-        if (t == 0 && k > k_lo && sg.sig_part) {
-          const int q = (k - 1) & 1;
-          sg.sig_part[blk * b.K_pad + (k - 1)] =
-              ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
-        }
-      }
       float2 y0[8], y1[8];
       {
         float2 w[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
         pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
+      }
+      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
+        // the previous template's four wave sums were written before the last barrier and
+        // are overwritten only after the next one
+        if (t == 0 && k > k_lo && sg.sig_part) {
+          const int q = (k - 1) & 1;
+          sg.sig_part[blk * b.K_pad + (k - 1)] =
+              ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
+        }
       }
       __syncthreads();
       {
@@ -1025,7 +1045,6 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
       if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
         float q = 0.0f;
         bool any = false;
-        [[maybe_unused]] const float tlo = MODE == MODE_ONEPASS ? sg.thr_lo[k] : 0.0f;
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
           const float rr = (outv(o) * scale) * inv[o];
@@ -1033,12 +1052,7 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
           if constexpr (MODE == MODE_ONEPASS) any = any || fabsf(rr) > tlo;
         }
         unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const unsigned flo = __shfl_xor((unsigned)(f & 0xFFFFFFFFull), o, 64);
-          const unsigned fhi = __shfl_xor((unsigned)(f >> 32), o, 64);
-          f += ((unsigned long long)fhi << 32) | flo;
-        }
+        f = wave_sum_u64(f);
         if ((t & 63) == 0) {
           if (sg.sig_part)
             sig_slot[k & 1][t >> 6] = f;
@@ -1119,12 +1133,7 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
           binmax[o] = -1.0f;
           binarg[o] = -1;
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const unsigned flo = __shfl_xor((unsigned)(fix & 0xFFFFFFFFull), o, 64);
-          const unsigned fhi = __shfl_xor((unsigned)(fix >> 32), o, 64);
-          fix += ((unsigned long long)fhi << 32) | flo;
-        }
+        fix = wave_sum_u64(fix);
         if ((t & 63) == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
         ++bin;
         left = nfd;
