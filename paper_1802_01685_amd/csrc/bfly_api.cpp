@@ -756,7 +756,12 @@ bf_status enqueue_onepass_tail_kernels(const bf_bank* bank, const SearchDev& sp_
   HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp_pass, stream), "k_finalize launch");
   HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
   HIP_TRY(launch_tails_check(table_dev, seg_slots, b, stream), "k_tails_check launch");
-  HIP_TRY(launch_tails_keep(table_dev, seg_slots, b, stream), "k_tails_keep launch");
+  // the tails of the series whose check passed: from the kept correlations (direct forms) or
+  // by transforming the listed (block, template) pairs again (FFT form)
+  if (b.precision == P_FFT)
+    HIP_TRY(launch_fft_pairs(table_dev, seg_slots, b, stream), "k_fft4k_pairs launch");
+  else
+    HIP_TRY(launch_tails_keep(table_dev, seg_slots, b, stream), "k_tails_keep launch");
   // the tails pass: every work item of a series whose check passed returns at once
   if (b.precision == P_FFT)
     HIP_TRY(launch_fft_pass(table_dev, main_blocks, b, sp_tails, stream), "k_fft tails launch");

@@ -813,8 +813,31 @@ __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* 
   }
 }
 
+// Thread 0 of k_fft4k: template k's rho^2 sum over the work-group's block (the four wave
+// sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
+// correlation above the kept bound; a flagged (block, template) pair is appended to the
+// series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
+template <int MODE>
+__device__ __forceinline__ void store_sig(const SegDesc& sg, const unsigned long long (&slot)[4],
+                                          int64_t blk, int k, int64_t k_pad) {
+  constexpr unsigned long long FLAG = 1ull << 63;
+  const unsigned long long s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3];
+  sg.sig_part[blk * k_pad + k] = ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG));
+  if constexpr (MODE == MODE_ONEPASS) {
+    if ((s0 | s1 | s2 | s3) & FLAG) {
+      const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
+      const int64_t per = sg.cand_cap / CAND_SHARDS;
+      const unsigned long long at = atomicAdd(sg.n_cand + shard, 1ull);
+      if ((int64_t)at < per) {
+        sg.c_tau[shard * per + (int64_t)at] = (int32_t)blk;
+        sg.c_k[shard * per + (int64_t)at] = k;
+      }
+    }
+  }
+}
+
 template <int SMAX, int MODE>
-__global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
+__global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
                                                   SearchDev p) {
   using namespace fft4k;
   static_assert(SMAX >= 1 && SMAX <= 16, "output slots");
@@ -877,6 +900,13 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
   }
   __syncthreads();
 
+  // Pass 1 of a template writes bufp, pass 2 reads it and writes bufq, pass 3 writes bufp
+  // back, pass 4 reads it; then the two swap.  The pass-1 buffer was last read in a pass 3,
+  // before that template's third barrier, so the swapping runs on across work items (a
+  // reset per item would let an item's first pass-1 writes meet the previous item's last
+  // pass-4 reads when an item has an odd number of templates).  The buffers follow the
+  // parity of a uniform template count, so no buffer pointer is carried in a VGPR.
+  unsigned it = 0;
   const int64_t total_tiles = hdr->total_tiles;
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     // Work-group i runs on XCD i mod 8 and each XCD takes its work-groups in order of i / 8.
@@ -925,18 +955,28 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
     // output o = 2 s + part sits at block position 2t + 512 s + part; it is a valid offset of
     // the series below this bound
     const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
+    // The single pass keeps the bin's argmax as 1 + (k - the bin's first template), two
+    // outputs to a register (0: none yet), to stay within 256 registers with sinv below.
+    constexpr bool PACK = MODE == MODE_ONEPASS;
     float binmax[NO];
-    int binarg[NO];
-    float inv[NO];     // sigma, tails and single-pass modes: 1/sqrt(E) as float (0 if invalid)
+    int binarg[PACK ? 1 : NO];
+    unsigned barg2[PACK ? (NO + 1) / 2 : 1];
+    // sigma, tails and single-pass modes: scale / sqrt(E) with 1/sqrt(E) rounded to float
+    // (0 if invalid); scale is a power of two, so y sinv = (y scale) (1/sqrt(E))_f32 exactly
+    float sinv[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       if constexpr (MODE == MODE_SEARCH || MODE == MODE_ONEPASS) {
         binmax[o] = -1.0f;
-        binarg[o] = -1;
+        if constexpr (PACK) {
+          if ((o & 1) == 0) barg2[o >> 1] = 0u;
+        } else {
+          binarg[o] = -1;
+        }
       }
       if constexpr (MODE != MODE_SEARCH) {
         const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
-        inv[o] = pos < pos_end ? (float)sg.inv_norm[tau_base + pos] : 0.0f;
+        sinv[o] = pos < pos_end ? scale * (float)sg.inv_norm[tau_base + pos] : 0.0f;
       }
     }
     const int k_lo = b_lo * nfd, k_hi = b_hi * nfd;
@@ -956,9 +996,9 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
     };
     load_h(k_lo);
     int bin = b_lo, left = nfd;
-    float2* bufp = lds;            // pass 1 writes here; the buffers swap every template
-    float2* bufq = lds + PADN;
-    for (int k = k_lo; k < k_hi; ++k) {
+    for (int k = k_lo; k < k_hi; ++k, ++it) {
+      float2* const bufp = lds + (it & 1u) * PADN;
+      float2* const bufq = lds + ((it + 1u) & 1u) * PADN;
       // the single pass's kept bound of this template, loaded before the transform needs
       // the scalar data path's waits
       [[maybe_unused]] const float tlo = MODE == MODE_ONEPASS ? sg.thr_lo[k] : 0.0f;
@@ -998,15 +1038,6 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
         for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
         pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
       }
-      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
-        // the previous template's four wave sums were written before the last barrier and
-        // are overwritten only after the next one
-        if (t == 0 && k > k_lo && sg.sig_part) {
-          const int q = (k - 1) & 1;
-          sg.sig_part[blk * b.K_pad + (k - 1)] =
-              ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
-        }
-      }
       __syncthreads();
       {
         float2 w[7];
@@ -1015,6 +1046,13 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
         pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
       }
       __syncthreads();
+      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
+        // the previous template's four wave sums were written before this template's first
+        // barrier and are overwritten only after the next template's third; by now the
+        // prefetch of the next template's spectrum has landed, so the store's wait is short
+        if (t == 0 && k > k_lo && sg.sig_part)
+          store_sig<MODE>(sg, sig_slot[(k - 1) & 1], blk, k - 1, b.K_pad);
+      }
       if constexpr (LEAN) {
         // pass 4's twiddle powers as running products of the bases
         float2 wa[7], wb[7];
@@ -1029,61 +1067,54 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
       } else {
         pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
       }
-      {
-        float2* s = bufp;
-        bufp = bufq;
-        bufq = s;
-      }
       // output slot o = 2 s + part: s even -> y0[s / 2], s odd -> y1[s / 2]
       auto outv = [&](int o) -> float {
         const int s = o >> 1;
         const float2 c = (s & 1) ? y1[s >> 1] : y0[s >> 1];
         return (o & 1) ? c.y : c.x;
       };
-      // rho = f32(d / sqrt(E)): (y scale) is exact and the product of two floats is exact in
-      // float64, so one float32 multiply rounds it exactly as the float64 route would
+      // rho = f32(d / sqrt(E)): y sinv is exact in float64 (a product of two floats), so one
+      // float32 multiply rounds it exactly as the float64 route would
       if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
         float q = 0.0f;
-        bool any = false;
+        float mr = 0.0f;   // the largest |rho| of the lane (single pass)
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
-          const float rr = (outv(o) * scale) * inv[o];
+          const float v = outv(o);
+          const float rr = v * sinv[o];
           q = fmaf(rr, rr, q);
-          if constexpr (MODE == MODE_ONEPASS) any = any || fabsf(rr) > tlo;
+          if constexpr (MODE == MODE_ONEPASS) {
+            mr = fmaxf(mr, fabsf(rr));
+            // the running maximum of the search (below), in the same sweep
+            const float a = fabsf(v);
+            const bool g = a > binmax[o];
+            const unsigned rel1 = (unsigned)(k - bin * nfd + 1);
+            const unsigned cur = barg2[o >> 1];
+            const unsigned nv =
+                (o & 1) ? ((cur & 0xFFFFu) | (rel1 << 16)) : ((cur & 0xFFFF0000u) | rel1);
+            barg2[o >> 1] = g ? nv : cur;
+            binmax[o] = g ? a : binmax[o];
+          }
         }
         unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
         f = wave_sum_u64(f);
+        // single pass: bit 63 of the wave's slot (free: the sums stay below 2^63) flags a
+        // correlation above the kept bound in this wave
+        if constexpr (MODE == MODE_ONEPASS)
+          if (__any(mr > tlo)) f |= 1ull << 63;
         if ((t & 63) == 0) {
           if (sg.sig_part)
-            sig_slot[k & 1][t >> 6] = f;
+            sig_slot[k & 1][__builtin_amdgcn_readfirstlane(t >> 6)] = f;
           else if (f != 0ull)
             atomicAdd(sg.sig_acc + k, f);
         }
         if constexpr (MODE == MODE_SIGMA) continue;
-        if (any) {
-          // candidates above the predicted threshold (rare): appended with one atomic each
-#pragma unroll
-          for (int o = 0; o < NO; ++o) {
-            const float rr = (outv(o) * scale) * inv[o];
-            if (fabsf(rr) > tlo) {
-              const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
-              const int64_t per = sg.cand_cap / CAND_SHARDS;
-              const unsigned long long slot = atomicAdd(sg.n_cand + shard, 1ull);
-              if ((int64_t)slot < per) {
-                const int64_t at = shard * per + (int64_t)slot;
-                sg.c_tau[at] = tau_base + 2 * t + 512 * (o >> 1) + (o & 1);
-                sg.c_k[at] = k;
-                sg.c_rho[at] = rr;
-              }
-            }
-          }
-        }
       }
       if constexpr (MODE == MODE_TAILS) {
         const float thr = sg.thr[k];
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
-          const float rf = (outv(o) * scale) * inv[o];
+          const float rf = outv(o) * sinv[o];
           if (fabsf(rf) > thr) {
             const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
             if ((int64_t)slot < sg.tail_cap) {
@@ -1097,12 +1128,14 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
         continue;
       }
       // running maximum over the bin's templates, lowest k on ties (k increases, strict >)
+      if constexpr (MODE == MODE_SEARCH) {
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        const float a = fabsf(outv(o));
-        const bool g = a > binmax[o];
-        binarg[o] = g ? k : binarg[o];
-        binmax[o] = g ? a : binmax[o];
+        for (int o = 0; o < NO; ++o) {
+          const float a = fabsf(outv(o));
+          const bool g = a > binmax[o];
+          binarg[o] = g ? k : binarg[o];
+          binmax[o] = g ? a : binmax[o];
+        }
       }
       if (--left == 0) {
         // end of bin: spectrogram row, spectrum sum, packed per-offset maxima
@@ -1110,7 +1143,14 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
           const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
-          if (pos < pos_end && binarg[o] >= 0) {
+          int ba;
+          if constexpr (PACK) {
+            const unsigned r1 = (barg2[o >> 1] >> (16 * (o & 1))) & 0xFFFFu;
+            ba = r1 ? bin * nfd + (int)r1 - 1 : -1;
+          } else {
+            ba = binarg[o];
+          }
+          if (pos < pos_end && ba >= 0) {
             const int tau = tau_base + pos;
             const float v = binmax[o] * scale;
             const double iv = sg.inv_norm[tau];
@@ -1126,12 +1166,16 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
               }
               fix += (unsigned long long)__double2ll_rn((double)s * SPEC_FIX_SCALE);
             }
-            const unsigned int kg = (unsigned int)(b.k_offset + binarg[o]);
+            const unsigned int kg = (unsigned int)(b.k_offset + ba);
             atomicMax(sg.mkey + tau,
                       ((unsigned long long)__float_as_uint(v) << 32) | (0xFFFFFFFFull - kg));
           }
           binmax[o] = -1.0f;
-          binarg[o] = -1;
+          if constexpr (PACK) {
+            if (o & 1) barg2[o >> 1] = 0u;   // after both outputs of the register
+          } else {
+            binarg[o] = -1;
+          }
         }
         fix = wave_sum_u64(fix);
         if ((t & 63) == 0 && fix != 0ull) atomicAdd(sg.spec_acc + bin, fix);
@@ -1142,10 +1186,149 @@ __global__ __launch_bounds__(256, MODE == MODE_ONEPASS ? 1 : 2) void k_fft4k(con
     if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
       // the item's last template
       __syncthreads();
-      if (t == 0 && k_hi > k_lo && sg.sig_part) {
-        const int q = (k_hi - 1) & 1;
-        sg.sig_part[blk * b.K_pad + (k_hi - 1)] =
-            ((sig_slot[q][0] + sig_slot[q][1]) + sig_slot[q][2]) + sig_slot[q][3];
+      if (t == 0 && k_hi > k_lo && sg.sig_part)
+        store_sig<MODE>(sg, sig_slot[(k_hi - 1) & 1], blk, k_hi - 1, b.K_pad);
+    }
+  }
+}
+
+// The tails of the (block, template) pairs the single pass of k_fft4k listed, for every
+// series whose check passed (redo = 0; a flagged series gets the full tails pass instead).
+// Per pair the transform of k_fft4k with the same operations in the same order, so rho is
+// the same bit for bit, then the compare against kappa sigma_k.  Work unit = (series, shard
+// of the pair list); a work-group takes a shard's pairs one after another.
+template <int SMAX>
+__global__ __launch_bounds__(256, 2) void k_fft4k_pairs(const BatchHdr* __restrict__ hdr,
+                                                        BankDev b) {
+  using namespace fft4k;
+  constexpr int NO = 2 * SMAX;
+  __shared__ float2 lds[2 * PADN];
+  __shared__ float2 hand[8];
+  __shared__ float2 hand_x[8];
+  __shared__ float2 tab2[7 * 8];
+  __shared__ float2 tab3[7 * 64];
+  const SegDesc* segs = hdr_segs(hdr);
+  const float2* spectra = (const float2*)b.data;
+  const int valid = 2 * M - b.L + 1;
+  const int t = threadIdx.x;
+  const float scale = 0.5f / (float)M;
+  const int nfd = b.n_fdot;
+  float2 wpair[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) wpair[r] = cis_rev<true>((float)(t + 512 * r) / (float)(2 * M));
+  const bool helper = t < 4;
+  const int ha_idx = 256 + 512 * (t & 3);
+  const float2 whelp = cis_rev<true>((float)ha_idx / (float)(2 * M));
+  const int j1w = t == 0 ? 256 : 512 - t;
+  for (int i = t; i < 7 * 64; i += 256) {
+    const int r = i / 64 + 1, m = i % 64;
+    tab3[i] = cis_rev<true>((float)((m * r) & 511) / 512.0f);
+    if (i < 7 * 8) {
+      const int r2 = i / 8 + 1, m2 = i % 8;
+      tab2[i] = cis_rev<true>((float)((m2 * r2) & 63) / 64.0f);
+    }
+  }
+  float2 tw4a[7], tw4b[7];
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    tw4a[r - 1] = cis_rev<true>((float)((t * r) & 4095) / 4096.0f);
+    tw4b[r - 1] = cis_rev<true>((float)(((t + 256) * r) & 4095) / 4096.0f);
+  }
+  __syncthreads();
+
+  const unsigned va = 8u * (unsigned)t, vb = 8u * (512u - (unsigned)t);
+  unsigned it = 0;   // pairs so far: the LDS buffers alternate as in k_fft4k
+  const int n_units = hdr->n_segs * CAND_SHARDS;
+  for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+    const SegDesc& sg = segs[unit / CAND_SHARDS];
+    if (!sg.redo || sg.redo[0] != 0u || !sg.c_tau) continue;
+    const int shard = unit % CAND_SHARDS;
+    const int64_t per = sg.cand_cap / CAND_SHARDS;
+    const int64_t n = min((int64_t)sg.n_cand[shard], per);
+    for (int64_t j = 0; j < n; ++j, ++it) {
+      const int64_t e = shard * per + j;
+      const int64_t blk = sg.c_tau[e];
+      const int k = sg.c_k[e];
+      const int tau_base = (int)(blk * valid);
+      const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
+      const float2* hk = spectra + (int64_t)k * (M + 2);
+      float2 xa[8], xb[8], ha[8], hb[8];
+      {
+        const __amdgpu_buffer_rsrc_t xr = row_rsrc(xsrc);
+        const __amdgpu_buffer_rsrc_t hr = row_rsrc(hk);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          xa[r] = row_load(xr, va, 4096u * r);
+          xb[r] = row_load(xr, vb, 4096u * (7 - r));
+          ha[r] = row_load(hr, va, 4096u * r);
+          hb[r] = row_load(hr, vb, 4096u * (7 - r));
+        }
+      }
+      const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
+      float2* const bufp = lds + (it & 1u) * PADN;
+      float2* const bufq = lds + ((it + 1u) & 1u) * PADN;
+      float2 v0[8], v1[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) mirror_pair(ha[r], xa[r], hb[r], xb[r], wpair[r], v0[r], v1[7 - r]);
+      if (helper) {
+        hand_x[2 * t] = xsrc[ha_idx];
+        hand_x[2 * t + 1] = xsrc[M - ha_idx];
+        float2 ya, yb;
+        mirror_pair(hk[ha_idx], hand_x[2 * t], hk[M - ha_idx], hand_x[2 * t + 1], whelp, ya, yb);
+        hand[t] = ya;
+        hand[7 - t] = yb;
+      }
+      if (t == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v1[r] = hand[r];
+      }
+      dft<8, true>(v0);
+      dft<8, true>(v1);
+      {
+        float2* w0 = bufp + 9 * t;
+        float2* w1 = bufp + 9 * j1w;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          w0[r] = v0[r];
+          w1[r] = v1[r];
+        }
+      }
+      __syncthreads();
+      float2 y0[8], y1[8];
+      {
+        float2 w[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
+        pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
+      }
+      __syncthreads();
+      {
+        float2 w[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) w[r] = tab3[64 * r + (t & 63)];
+        pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
+      }
+      __syncthreads();
+      pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+      const float thr = sg.thr[k];
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        const int s = o >> 1;
+        const float2 c = (s & 1) ? y1[s >> 1] : y0[s >> 1];
+        const int pos = 2 * t + 512 * s + (o & 1);
+        if (pos >= pos_end) continue;
+        // the value k_fft4k forms: y (scale / sqrt(E)) with 1/sqrt(E) rounded to float
+        const float sv = scale * (float)sg.inv_norm[tau_base + pos];
+        const float rf = ((o & 1) ? c.y : c.x) * sv;
+        if (fabsf(rf) > thr) {
+          const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
+          if ((int64_t)slot < sg.tail_cap) {
+            sg.t_tau[slot] = tau_base + pos;
+            sg.t_k[slot] = (int32_t)(b.k_offset + k);
+            sg.t_rho[slot] = rf;
+          }
+          atomicAdd(sg.t_bins + k / nfd, 1u);
+        }
       }
     }
   }
@@ -1169,7 +1352,26 @@ bool fft4k_enabled() {
 
 }  // namespace
 
-bool fft_onepass_available(const BankDev& b) { return b.fft_m == 4096 && fft4k_enabled(); }
+bool fft_onepass_available(const BankDev& b) {
+  return b.fft_m == 4096 && fft4k_enabled() && b.n_fdot < 65535;
+}
+
+hipError_t launch_fft_pairs(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                            hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>((int64_t)seg_slots * CAND_SHARDS, 512);
+  switch (fft4k_slots(b)) {
+    case 9:
+      hipLaunchKernelGGL(k_fft4k_pairs<9>, dim3(grid), dim3(256), 0, s, hdr, b);
+      break;
+    case 13:
+      hipLaunchKernelGGL(k_fft4k_pairs<13>, dim3(grid), dim3(256), 0, s, hdr, b);
+      break;
+    default:
+      hipLaunchKernelGGL(k_fft4k_pairs<16>, dim3(grid), dim3(256), 0, s, hdr, b);
+      break;
+  }
+  return hipGetLastError();
+}
 
 namespace {
 

@@ -197,7 +197,9 @@ struct SearchDev {
 };
 
 // Contraction passes: the search; the search that also sums rho^2 per template; the pass
-// that extracts the tails above kappa * sigma_k (and does nothing else).
+// that extracts the tails above kappa * sigma_k (and does nothing else); the FFT form's
+// single pass (search, rho^2 sums, and the (template, block) pairs holding a correlation
+// above the kept bound).
 enum MainMode { MODE_SEARCH = 0, MODE_SIGMA = 1, MODE_TAILS = 2, MODE_ONEPASS = 3 };
 
 // Single-pass tail search: the fraction of the predicted sigma below which candidates are
@@ -257,8 +259,13 @@ hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev&
 // overflowed), and k_tails_keep moves the candidates above the exact thresholds into the
 // tail lists of every series not flagged; the tails pass then runs only for flagged series.
 int pred_points(const BankDev& b);
-// The FFT form's search kernel has the single-pass mode (N = 8192).
+// The FFT form's search kernel has the single-pass mode (N = 8192, fewer than 2^16
+// templates per f0 bin).  Its candidates are (block, template) pairs, not correlations:
+// c_tau holds the block and c_k the template, and launch_fft_pairs extracts the tails of the
+// listed pairs of every series whose check passed.
 bool fft_onepass_available(const BankDev& b);
+hipError_t launch_fft_pairs(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                            hipStream_t s);
 hipError_t launch_acf(const BatchHdr* hdr, int32_t seg_slots, int L, hipStream_t s);
 hipError_t launch_qspec(const BatchHdr* hdr, int32_t seg_slots, int L, int pred_n,
                         hipStream_t s);

@@ -1341,10 +1341,18 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
     const int64_t kbase = kt * (32 * MB);
     const int r_lo = (int)((k_lo > kbase ? k_lo : kbase) - kbase);        // rows owned
     const int r_hi = (int)((k_hi < kbase + (32 * MB) ? k_hi : kbase + (32 * MB)) - kbase);
+    // rho of the tail modes: (d dscale) (1/sqrt(E) rounded to float32) in float32.  dscale
+    // is a power of two, so d dscale is exact and the product of two floats is exact in
+    // float64: this is that product rounded once.
+    float invf[NB];
+    if constexpr (MODE != MODE_SEARCH) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) invf[j] = (float)inv[j];
+    }
     if constexpr (MODE == MODE_TAILS) {
-      // rho = d / sqrt(E) exactly as the butterfly output is formed; every owned (tau, k)
-      // with |rho| > kappa * sigma_k is appended to the series' list and counted in its bin.
-      // (rows as in the search epilogue: c + 4h, the ownership test on the immediate c)
+      // every owned (tau, k) with |rho| > kappa * sigma_k is appended to the series' list
+      // and counted in its bin (rows as in the search epilogue: c + 4h, the ownership test
+      // on the immediate c)
       const float* th = sg.thr + kbase + 4 * h;
       const int qh = r_lo - 4 * h;
       const unsigned span = (unsigned)(r_hi - r_lo);
@@ -1359,7 +1367,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int c = 32 * t + 8 * g + i;
-              const float rf = (float)((double)(acc[t][j][4 * g + i] * dscale) * inv[j]);
+              const float rf = (acc[t][j][4 * g + i] * dscale) * invf[j];
               if (fabsf(rf) > tv[i] && (unsigned)(c - qh) < span) {
                 const int64_t kl = kbase + c + 4 * h;
                 const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
@@ -1436,24 +1444,40 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
       // bit w), so lane n of a half ends with the sum for slot n = 16t + 4g + i4.  The sums
       // are added to the per-template fixed-point totals, exact and order-independent.
       static_assert(MB == 2, "the sigma pass is compiled for two template blocks");
+      // single-pass tail search: every owned (tau, k) with |rho| above the predicted lower
+      // threshold is kept as a candidate (rows and ownership as in the tails pass).  One
+      // sweep sums rho^2 and flags a lane holding any candidate (a row it does not own
+      // compares against +inf); the rare flagged lanes append theirs in a second sweep.
+      const bool cand = sg.c_tau != nullptr;
+      const float* th = sg.thr_lo + kbase + 4 * h;
+      const int qh = r_lo - 4 * h;
+      const unsigned span = (unsigned)(r_hi - r_lo);
       float q[32];
 #pragma unroll
       for (int v = 0; v < 32; ++v) q[v] = 0.0f;
+      bool any = false;
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
+      for (int t = 0; t < MB; ++t)
 #pragma unroll
-        for (int t = 0; t < MB; ++t)
+        for (int g = 0; g < 4; ++g) {
+          float tv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+          if (cand) {
+            const float4 t4 = *(const float4*)(th + 32 * t + 8 * g);
+            tv[0] = t4.x; tv[1] = t4.y; tv[2] = t4.z; tv[3] = t4.w;
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const float rf = (float)((double)(acc[t][j][v] * dscale) * inv[j]);
-            q[16 * t + v] = fmaf(rf, rf, q[16 * t + v]);
+            for (int i = 0; i < 4; ++i)
+              tv[i] = (unsigned)(32 * t + 8 * g + i - qh) < span ? tv[i] : INFINITY;
           }
-      if (sg.c_tau) {
-        // single-pass tail search: every owned (tau, k) with |rho| above the predicted lower
-        // threshold is kept as a candidate (rows and ownership as in the tails pass)
-        const float* th = sg.thr_lo + kbase + 4 * h;
-        const int qh = r_lo - 4 * h;
-        const unsigned span = (unsigned)(r_hi - r_lo);
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float rf = (acc[t][j][4 * g + i] * dscale) * invf[j];
+              q[16 * t + 4 * g + i] = fmaf(rf, rf, q[16 * t + 4 * g + i]);
+              any = any || fabsf(rf) > tv[i];
+            }
+        }
+      if (any) {
 #pragma unroll
         for (int t = 0; t < MB; ++t)
 #pragma unroll
@@ -1465,7 +1489,7 @@ __device__ __forceinline__ void main_item(const BatchHdr* __restrict__ hdr, int6
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 const int c = 32 * t + 8 * g + i;
-                const float rf = (float)((double)(acc[t][j][4 * g + i] * dscale) * inv[j]);
+                const float rf = (acc[t][j][4 * g + i] * dscale) * invf[j];
                 if (fabsf(rf) > tv[i] && (unsigned)(c - qh) < span) {
                   const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
                   const int64_t per = sg.cand_cap / CAND_SHARDS;

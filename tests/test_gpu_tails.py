@@ -170,15 +170,18 @@ def _tails_run(bf, bank, xs32, kappa, env, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["fft", "f16f6", "fp32", "bf16x3", "fp8"])
-def test_single_pass_equals_two_pass(bf, prec, monkeypatch):
+@pytest.mark.parametrize("shape", [(6, 10), (5, 7)])
+def test_single_pass_equals_two_pass(bf, prec, shape, monkeypatch):
     """Sec. 2.2 predicts sigma before the search (Parseval): the single-pass tail search keeps
     the pairs above a predicted lower threshold while it sums rho^2 and selects the tails
     among them afterwards.  Its search outputs, sigma, tails and counts equal the two-pass
     search's bit for bit -- by default, when its check of the prediction fails (margin above
-    1: every series falls back to the tails pass) and when its candidates overflow."""
+    1: every series falls back to the tails pass) and when its candidates overflow.  The
+    5 x 7 bank gives odd template counts per bin range (the FFT form's single pass transforms
+    two templates at a time)."""
     from synth import chirp_samples
-    p = BankParams(fs=1024.0, L=1024, n_f0=6, n_fdot=10, f0_min=40.0, f0_max=300.0,
-                   fdot_min=-150.0, fdot_max=150.0)         # L = 1024: the FFT form at N = 8192
+    p = BankParams(fs=1024.0, L=1024, n_f0=shape[0], n_fdot=shape[1], f0_min=40.0,
+                   f0_max=300.0, fdot_min=-150.0, fdot_max=150.0)   # L = 1024: N = 8192
     gr = O.grid(p)
     sig, _ = chirp_samples(30000, p.fs, 7000 / p.fs, gr.f0[23], gr.fdot[23])
     a = (white_noise(30000, 41) + 0.4 * sig).astype(np.float32)
