@@ -364,8 +364,10 @@ def tails_leg(bf, torch, p, xs, prec, kappa, steps):
     sig = tails[0]["sigma"].cpu().numpy()
     res = {"kappa": kappa, "precision_form": prec, "ms_per_step": wall / steps * 1e3,
            "correlations_per_s": corr * steps / wall,
-           "passes": "1 (a second only for a series whose predicted threshold check fails)"
-                     if prec != "fft" or fft_points(p.L) == 4096 else 3,
+           "passes": ("1, then the listed (block, template) pairs transformed again"
+                      if prec == "fft" else "1") +
+                     " (a second full pass only for a series whose predicted threshold check "
+                     "fails)" if prec != "fft" or fft_points(p.L) == 4096 else 3,
            "n_tails": n_tails, "sigma_median_x_sqrtL": float(np.median(sig) * np.sqrt(p.L)),
            "series": ["data", "control"][:len(xs)]}
     del bank, outs, tails, ws

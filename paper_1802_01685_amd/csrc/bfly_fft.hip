@@ -817,20 +817,34 @@ __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* 
 // sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
 // correlation above the kept bound; a flagged (block, template) pair is appended to the
 // series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
+// Where thread 0 of k_fft4k puts a template's sums: the series' pointers, read once per work
+// item so that no scalar load is in flight during the template loop (a scalar load returns
+// out of order, which makes every LDS wait of a pass wait for all of its reads).
+struct SigOut {
+  unsigned long long* part;   // [blocks][K_pad] rho^2 partial sums
+  unsigned long long* n_cand; // [CAND_SHARDS] pair counters (single pass)
+  int32_t* c_blk;             // listed pairs: block
+  int32_t* c_k;               //               template
+  int64_t per;                // pairs per shard
+};
+
+// Thread 0 of k_fft4k: template k's rho^2 sum over the work-group's block (the four wave
+// sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
+// correlation above the kept bound; a flagged (block, template) pair is appended to the
+// series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
 template <int MODE>
-__device__ __forceinline__ void store_sig(const SegDesc& sg, const unsigned long long (&slot)[4],
+__device__ __forceinline__ void store_sig(const SigOut& so, const unsigned long long (&slot)[4],
                                           int64_t blk, int k, int64_t k_pad) {
   constexpr unsigned long long FLAG = 1ull << 63;
   const unsigned long long s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3];
-  sg.sig_part[blk * k_pad + k] = ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG));
+  so.part[blk * k_pad + k] = ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG));
   if constexpr (MODE == MODE_ONEPASS) {
     if ((s0 | s1 | s2 | s3) & FLAG) {
       const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
-      const int64_t per = sg.cand_cap / CAND_SHARDS;
-      const unsigned long long at = atomicAdd(sg.n_cand + shard, 1ull);
-      if ((int64_t)at < per) {
-        sg.c_tau[shard * per + (int64_t)at] = (int32_t)blk;
-        sg.c_k[shard * per + (int64_t)at] = k;
+      const unsigned long long at = atomicAdd(so.n_cand + shard, 1ull);
+      if ((int64_t)at < so.per) {
+        so.c_blk[shard * so.per + (int64_t)at] = (int32_t)blk;
+        so.c_k[shard * so.per + (int64_t)at] = k;
       }
     }
   }
@@ -995,13 +1009,25 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       hhb = row_load(hr, 8u * (unsigned)(M - ha_idx), 0u);
     };
     load_h(k_lo);
+    [[maybe_unused]] SigOut so;
+    if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS)
+      so = SigOut{sg.sig_part, sg.n_cand, sg.c_tau, sg.c_k, sg.cand_cap / CAND_SHARDS};
+    // the single pass's kept bounds: a vector load one template ahead, on the same counter
+    // as the spectrum prefetch (a scalar load would be waited for with the LDS reads)
+    [[maybe_unused]] __amdgpu_buffer_rsrc_t thr_r;
+    [[maybe_unused]] float tlo_next = 0.0f;
+    if constexpr (MODE == MODE_ONEPASS) {
+      const int64_t bytes = (int64_t)(k_hi - k_lo) * 4;
+      thr_r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(sg.thr_lo + k_lo), (short)0,
+                                                (int)(bytes < 0x7FFFFFF0 ? bytes : 0x7FFFFFF0),
+                                                0x00020000);
+      tlo_next = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(thr_r, 0u, 0u, 0));
+    }
     int bin = b_lo, left = nfd;
     for (int k = k_lo; k < k_hi; ++k, ++it) {
       float2* const bufp = lds + (it & 1u) * PADN;
       float2* const bufq = lds + ((it + 1u) & 1u) * PADN;
-      // the single pass's kept bound of this template, loaded before the transform needs
-      // the scalar data path's waits
-      [[maybe_unused]] const float tlo = MODE == MODE_ONEPASS ? sg.thr_lo[k] : 0.0f;
+      [[maybe_unused]] const float tlo = tlo_next;
       // ---- spectrum product, post-processing and the first radix-8 pass, in registers
       float2 v0[8], v1[8];
 #pragma unroll
@@ -1014,6 +1040,9 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         hand[t] = ya;
         hand[7 - t] = yb;
       }
+      if constexpr (MODE == MODE_ONEPASS)
+        tlo_next = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 thr_r, 0u, 4u * (unsigned)(min(k + 1, k_hi - 1) - k_lo), 0));
       load_h(min(k + 1, k_hi - 1));   // unconditional (the last one repeats a row)
       if (t == 0) {
         // the helpers are lanes of this wave: their LDS writes precede these reads
@@ -1050,8 +1079,8 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         // the previous template's four wave sums were written before this template's first
         // barrier and are overwritten only after the next template's third; by now the
         // prefetch of the next template's spectrum has landed, so the store's wait is short
-        if (t == 0 && k > k_lo && sg.sig_part)
-          store_sig<MODE>(sg, sig_slot[(k - 1) & 1], blk, k - 1, b.K_pad);
+        if (t == 0 && k > k_lo && so.part)
+          store_sig<MODE>(so, sig_slot[(k - 1) & 1], blk, k - 1, b.K_pad);
       }
       if constexpr (LEAN) {
         // pass 4's twiddle powers as running products of the bases
@@ -1088,10 +1117,11 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
             // the running maximum of the search (below), in the same sweep
             const float a = fabsf(v);
             const bool g = a > binmax[o];
+            // the low (even o) or high (odd o) half of the register becomes rel1: one byte
+            // permutation of {cur, rel1} (bytes 0-3 of rel1, 4-7 of cur)
             const unsigned rel1 = (unsigned)(k - bin * nfd + 1);
             const unsigned cur = barg2[o >> 1];
-            const unsigned nv =
-                (o & 1) ? ((cur & 0xFFFFu) | (rel1 << 16)) : ((cur & 0xFFFF0000u) | rel1);
+            const unsigned nv = __builtin_amdgcn_perm(cur, rel1, (o & 1) ? 0x01000504u : 0x07060100u);
             barg2[o >> 1] = g ? nv : cur;
             binmax[o] = g ? a : binmax[o];
           }
@@ -1103,7 +1133,7 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         if constexpr (MODE == MODE_ONEPASS)
           if (__any(mr > tlo)) f |= 1ull << 63;
         if ((t & 63) == 0) {
-          if (sg.sig_part)
+          if (so.part)
             sig_slot[k & 1][__builtin_amdgcn_readfirstlane(t >> 6)] = f;
           else if (f != 0ull)
             atomicAdd(sg.sig_acc + k, f);
@@ -1186,8 +1216,8 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
     if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
       // the item's last template
       __syncthreads();
-      if (t == 0 && k_hi > k_lo && sg.sig_part)
-        store_sig<MODE>(sg, sig_slot[(k_hi - 1) & 1], blk, k_hi - 1, b.K_pad);
+      if (t == 0 && k_hi > k_lo && so.part)
+        store_sig<MODE>(so, sig_slot[(k_hi - 1) & 1], blk, k_hi - 1, b.K_pad);
     }
   }
 }
