@@ -1228,7 +1228,7 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
 // the same bit for bit, then the compare against kappa sigma_k.  Work unit = (series, shard
 // of the pair list); a work-group takes a shard's pairs one after another.
 template <int SMAX>
-__global__ __launch_bounds__(256, 2) void k_fft4k_pairs(const BatchHdr* __restrict__ hdr,
+__global__ __launch_bounds__(256, 1) void k_fft4k_pairs(const BatchHdr* __restrict__ hdr,
                                                         BankDev b) {
   using namespace fft4k;
   constexpr int NO = 2 * SMAX;
@@ -1275,39 +1275,70 @@ __global__ __launch_bounds__(256, 2) void k_fft4k_pairs(const BatchHdr* __restri
     const int shard = unit % CAND_SHARDS;
     const int64_t per = sg.cand_cap / CAND_SHARDS;
     const int64_t n = min((int64_t)sg.n_cand[shard], per);
+    if (n <= 0) continue;
+    // A shard's pairs come in runs of one block (a work-group appends the pairs of its
+    // current block), so the block's spectrum and scales are reloaded only when the block
+    // changes; the next pair's template spectrum is loaded while the current one transforms.
+    const int64_t e0 = shard * per;
+    int64_t blk_n = sg.c_tau[e0];
+    int k_n = sg.c_k[e0];
+    float2 ha[8], hb[8], hha, hhb;
+    auto load_h = [&](int k) {
+      const __amdgpu_buffer_rsrc_t hr = row_rsrc(spectra + (int64_t)k * (M + 2));
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        ha[r] = row_load(hr, va, 4096u * r);
+        hb[r] = row_load(hr, vb, 4096u * (7 - r));
+      }
+      hha = row_load(hr, 8u * (unsigned)ha_idx, 0u);
+      hhb = row_load(hr, 8u * (unsigned)(M - ha_idx), 0u);
+    };
+    load_h(k_n);
+    int64_t cur_blk = -1;
+    int tau_base = 0;
+    float2 xa[8], xb[8];
+    float sinv[NO];
     for (int64_t j = 0; j < n; ++j, ++it) {
-      const int64_t e = shard * per + j;
-      const int64_t blk = sg.c_tau[e];
-      const int k = sg.c_k[e];
-      const int tau_base = (int)(blk * valid);
-      const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
-      const float2* hk = spectra + (int64_t)k * (M + 2);
-      float2 xa[8], xb[8], ha[8], hb[8];
-      {
+      const int64_t blk = blk_n;
+      const int k = k_n;
+      if (blk != cur_blk) {
+        cur_blk = blk;
+        tau_base = (int)(blk * valid);
+        const float2* xsrc = sg.xspec + blk * (int64_t)(M + 2);
         const __amdgpu_buffer_rsrc_t xr = row_rsrc(xsrc);
-        const __amdgpu_buffer_rsrc_t hr = row_rsrc(hk);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           xa[r] = row_load(xr, va, 4096u * r);
           xb[r] = row_load(xr, vb, 4096u * (7 - r));
-          ha[r] = row_load(hr, va, 4096u * r);
-          hb[r] = row_load(hr, vb, 4096u * (7 - r));
+        }
+        if (helper) {
+          hand_x[2 * t] = xsrc[ha_idx];
+          hand_x[2 * t + 1] = xsrc[M - ha_idx];
+        }
+        // the scales k_fft4k forms: scale / sqrt(E) with 1/sqrt(E) rounded to float
+        const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          const int pos = 2 * t + 512 * (o >> 1) + (o & 1);
+          sinv[o] = pos < pos_end ? scale * (float)sg.inv_norm[tau_base + pos] : 0.0f;
         }
       }
-      const int pos_end = (int)min((int64_t)valid, sg.W - (int64_t)tau_base);
       float2* const bufp = lds + (it & 1u) * PADN;
       float2* const bufq = lds + ((it + 1u) & 1u) * PADN;
       float2 v0[8], v1[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) mirror_pair(ha[r], xa[r], hb[r], xb[r], wpair[r], v0[r], v1[7 - r]);
       if (helper) {
-        hand_x[2 * t] = xsrc[ha_idx];
-        hand_x[2 * t + 1] = xsrc[M - ha_idx];
         float2 ya, yb;
-        mirror_pair(hk[ha_idx], hand_x[2 * t], hk[M - ha_idx], hand_x[2 * t + 1], whelp, ya, yb);
+        mirror_pair(hha, hand_x[2 * t], hhb, hand_x[2 * t + 1], whelp, ya, yb);
         hand[t] = ya;
         hand[7 - t] = yb;
       }
+      if (j + 1 < n) {
+        blk_n = sg.c_tau[e0 + j + 1];
+        k_n = sg.c_k[e0 + j + 1];
+      }
+      load_h(k_n);   // unconditional (the last one repeats a row)
       if (t == 0) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) v1[r] = hand[r];
@@ -1345,15 +1376,11 @@ __global__ __launch_bounds__(256, 2) void k_fft4k_pairs(const BatchHdr* __restri
       for (int o = 0; o < NO; ++o) {
         const int s = o >> 1;
         const float2 c = (s & 1) ? y1[s >> 1] : y0[s >> 1];
-        const int pos = 2 * t + 512 * s + (o & 1);
-        if (pos >= pos_end) continue;
-        // the value k_fft4k forms: y (scale / sqrt(E)) with 1/sqrt(E) rounded to float
-        const float sv = scale * (float)sg.inv_norm[tau_base + pos];
-        const float rf = ((o & 1) ? c.y : c.x) * sv;
+        const float rf = ((o & 1) ? c.y : c.x) * sinv[o];
         if (fabsf(rf) > thr) {
           const unsigned long long slot = atomicAdd(sg.n_tails, 1ull);
           if ((int64_t)slot < sg.tail_cap) {
-            sg.t_tau[slot] = tau_base + pos;
+            sg.t_tau[slot] = tau_base + 2 * t + 512 * s + (o & 1);
             sg.t_k[slot] = (int32_t)(b.k_offset + k);
             sg.t_rho[slot] = rf;
           }
