@@ -742,7 +742,11 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
 // The sigma and tails modes are those of k_fft_main.
 namespace fft4k {
 constexpr int M = 4096;
-constexpr int PADN = M + M / 8;
+constexpr int PADN = M + M / 8;   // the largest stage layout (SH = 3)
+// stage layouts: first pass -> second (S1), second -> third (S2), third -> fourth (S3).
+// Measured on the light-curve share: (5, 3, 0) 229-230 ms per search, (4, 3, 0) 230-231,
+// (3, 3, 0) 235, (3, 3, 3) 233-235.
+constexpr int S1 = 5, S2 = 3, S3 = 0;
 constexpr unsigned ROW_BYTES = (M + 2) * 8;   // one spectrum row (bins 0..M, padded)
 }  // namespace fft4k
 
@@ -776,21 +780,34 @@ __device__ __forceinline__ void mirror_pair(float2 ha, float2 xa, float2 hb, flo
   yb = make_float2(e.x + o.y, o.x - e.y);
 }
 
-// One radix-8 Stockham pass of two butterflies (t and t + 256) from `src` to `dst` with
-// sub-transform size NS before the pass; input r of butterfly t is twiddled by wa[r - 1] and
-// of butterfly t + 256 by wb[r - 1].  KEEP leaves the outputs in y0, y1 instead of writing
-// them.
-template <int NS, bool KEEP>
+// LDS layouts of the M = 4096 transform: element i of a stage's buffer sits at
+// i + (i >> SH) (one pad slot per 2^SH elements; SH = 0: no padding).  Each stage's layout
+// suits its writer and its reader: the first pass writes 8 consecutive points per thread
+// (lanes 8 elements apart), the second writes runs of 8 points 64 apart, the third
+// contiguous runs; every pass reads contiguous runs.  Padding every 8 spreads the first two
+// write patterns over all banks but makes each 32-lane read of a contiguous run wrap onto
+// banks it already used; contiguous writes and reads need no padding at all.
+template <int SH>
+__device__ __forceinline__ int padk(int i) { return SH ? i + (i >> SH) : i; }
+
+// One radix-8 Stockham pass of two butterflies (t and t + 256) from `src` (layout SP) to
+// `dst` (layout DP) with sub-transform size NS before the pass; input r of butterfly t is
+// twiddled by wa[r - 1] and of butterfly t + 256 by wb[r - 1].  KEEP leaves the outputs in
+// y0, y1 instead of writing them.
+template <int NS, bool KEEP, int SP, int DP>
 __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* __restrict__ dst,
                                         const float2 (&wa)[7], const float2 (&wb)[7],
                                         float2 (&y0)[8], float2 (&y1)[8]) {
   const int t = threadIdx.x;
-  // pad(t + 512 r) = pad(t) + 576 r and pad(t + 256 + 512 r) = pad(t) + 288 + 576 r
-  const float2* rd = src + pad(t);
+  // 512 r and 256 are multiples of 2^SP: padk(t + 512 r) = padk(t) + padk(512 r), and
+  // padk(t + 256 + 512 r) = padk(t) + padk(256) + padk(512 r)
+  constexpr int R1 = SP ? 512 + (512 >> SP) : 512;
+  constexpr int HALF = SP ? 256 + (256 >> SP) : 256;
+  const float2* rd = src + padk<SP>(t);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    y0[r] = rd[576 * r];
-    y1[r] = rd[288 + 576 * r];
+    y0[r] = rd[R1 * r];
+    y1[r] = rd[HALF + R1 * r];
   }
 #pragma unroll
   for (int r = 1; r < 8; ++r) {
@@ -801,22 +818,20 @@ __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* 
   dft<8, true>(y1);
   if constexpr (!KEEP) {
     // output r of butterfly j goes to point o + r NS, o = (j - j mod NS) 8 + j mod NS; NS is a
-    // multiple of 8, so pad(o + r NS) = pad(o) + r (NS + NS / 8)
+    // multiple of 2^DP, so padk(o + r NS) = padk(o) + r padk(NS)
+    static_assert(DP == 0 || NS % (1 << DP) == 0, "stride must keep the pad phase");
+    constexpr int RS = DP ? NS + (NS >> DP) : NS;
     const int m0 = t & (NS - 1), m1 = (t + 256) & (NS - 1);
-    float2* w0 = dst + pad((t - m0) * 8 + m0);
-    float2* w1 = dst + pad((t + 256 - m1) * 8 + m1);
+    float2* w0 = dst + padk<DP>((t - m0) * 8 + m0);
+    float2* w1 = dst + padk<DP>((t + 256 - m1) * 8 + m1);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      w0[r * (NS + NS / 8)] = y0[r];
-      w1[r * (NS + NS / 8)] = y1[r];
+      w0[r * RS] = y0[r];
+      w1[r * RS] = y1[r];
     }
   }
 }
 
-// Thread 0 of k_fft4k: template k's rho^2 sum over the work-group's block (the four wave
-// sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
-// correlation above the kept bound; a flagged (block, template) pair is appended to the
-// series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
 // Where thread 0 of k_fft4k puts a template's sums: the series' pointers, read once per work
 // item so that no scalar load is in flight during the template loop (a scalar load returns
 // out of order, which makes every LDS wait of a pass wait for all of its reads).
@@ -1051,9 +1066,9 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       }
       dft<8, true>(v0);
       dft<8, true>(v1);
-      // point 8 j + r of the first pass's output: pad = 9 j + r
-      float2* w0 = bufp + 9 * t;
-      float2* w1 = bufp + 9 * j1w;
+      // point 8 j + r of the first pass's output at padk<S1>(8 j + r) = padk<S1>(8 j) + r
+      float2* w0 = bufp + padk<S1>(8 * t);
+      float2* w1 = bufp + padk<S1>(8 * j1w);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         w0[r] = v0[r];
@@ -1065,14 +1080,14 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         float2 w[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
-        pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
+        pass8x2<8, false, S1, S2>(bufp, bufq, w, w, y0, y1);
       }
       __syncthreads();
       {
         float2 w[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) w[r] = tab3[64 * r + (t & 63)];
-        pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
+        pass8x2<64, false, S2, S3>(bufq, bufp, w, w, y0, y1);
       }
       __syncthreads();
       if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
@@ -1092,9 +1107,9 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
           wa[r] = cmul(wa[r - 1], tw4a[0]);
           wb[r] = cmul(wb[r - 1], tw4b[0]);
         }
-        pass8x2<512, true>(bufp, bufq, wa, wb, y0, y1);
+        pass8x2<512, true, S3, 0>(bufp, bufq, wa, wb, y0, y1);
       } else {
-        pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+        pass8x2<512, true, S3, 0>(bufp, bufq, tw4a, tw4b, y0, y1);
       }
       // output slot o = 2 s + part: s even -> y0[s / 2], s odd -> y1[s / 2]
       auto outv = [&](int o) -> float {
@@ -1346,8 +1361,8 @@ __global__ __launch_bounds__(256, 1) void k_fft4k_pairs(const BatchHdr* __restri
       dft<8, true>(v0);
       dft<8, true>(v1);
       {
-        float2* w0 = bufp + 9 * t;
-        float2* w1 = bufp + 9 * j1w;
+        float2* w0 = bufp + padk<S1>(8 * t);
+        float2* w1 = bufp + padk<S1>(8 * j1w);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           w0[r] = v0[r];
@@ -1360,17 +1375,17 @@ __global__ __launch_bounds__(256, 1) void k_fft4k_pairs(const BatchHdr* __restri
         float2 w[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) w[r] = tab2[8 * r + (t & 7)];
-        pass8x2<8, false>(bufp, bufq, w, w, y0, y1);
+        pass8x2<8, false, S1, S2>(bufp, bufq, w, w, y0, y1);
       }
       __syncthreads();
       {
         float2 w[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) w[r] = tab3[64 * r + (t & 63)];
-        pass8x2<64, false>(bufq, bufp, w, w, y0, y1);
+        pass8x2<64, false, S2, S3>(bufq, bufp, w, w, y0, y1);
       }
       __syncthreads();
-      pass8x2<512, true>(bufp, bufq, tw4a, tw4b, y0, y1);
+      pass8x2<512, true, S3, 0>(bufp, bufq, tw4a, tw4b, y0, y1);
       const float thr = sg.thr[k];
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
