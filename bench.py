@@ -448,7 +448,7 @@ def main() -> int:
                     help="forms timed beside the headline ('' skips)")
     ap.add_argument("--cpu-offsets", type=int, default=1024,
                     help="oracle offsets per series of the sample (0 skips the oracle leg)")
-    ap.add_argument("--batch-forms", default="f16f6,bf16x3,fp32",
+    ap.add_argument("--batch-forms", default="fft,f16f6,bf16x3,fp32",
                     help="forms timed on the 84-series batch ('' skips the leg)")
     ap.add_argument("--tails-kappa", type=float, default=5.0,
                     help="search depth of the tail leg (0 skips it)")

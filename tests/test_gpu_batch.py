@@ -76,7 +76,7 @@ def batch84():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["fft", "bf16x3", "fp32"])
 def test_all_84_series_in_one_batch(bf, prec, batch84):
     p, batch, checks, orcs = batch84
     bank = bf.bank_create(p, prec)
