@@ -106,9 +106,9 @@ struct SegDesc {
   // single-pass tail search (null when the tails are extracted by a second pass): the
   // predicted lower thresholds, the candidates above them and the check of the prediction
   float* thr_lo;                 // [K_pad] kappa * margin * predicted sigma_k (+inf past K)
-  int32_t* c_tau;                // [cand_cap] candidate offsets
+  int32_t* c_tau;                // [cand_cap] candidate offsets (FFT form: blocks)
   int32_t* c_k;                  // [cand_cap] candidate local template indices
-  float* c_rho;                  // [cand_cap] candidate rho (signed)
+  float* c_rho;                  // [cand_cap] candidate rho (signed; unused by the FFT form)
   unsigned long long* n_cand;    // [CAND_SHARDS] candidates found per shard
   int64_t cand_cap;              // CAND_SHARDS shards of cand_cap / CAND_SHARDS entries
   uint32_t* redo;                // [1] 1: the prediction did not hold, run the tails pass
@@ -256,8 +256,9 @@ hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev&
 // from the bank's spectra (FFT form) or from spectra made on the fly (direct forms).  After
 // the pass that sums rho^2 and keeps candidates above those thresholds: k_tails_check flags
 // a series whose exact thresholds fall below the predicted ones (or whose candidates
-// overflowed), and k_tails_keep moves the candidates above the exact thresholds into the
-// tail lists of every series not flagged; the tails pass then runs only for flagged series.
+// overflowed), and k_tails_keep (direct forms) moves the candidates above the exact
+// thresholds into the tail lists of every series not flagged, or launch_fft_pairs (FFT form)
+// transforms its listed pairs again; the tails pass then runs only for flagged series.
 int pred_points(const BankDev& b);
 // The FFT form's search kernel has the single-pass mode (N = 8192, fewer than 2^16
 // templates per f0 bin).  Its candidates are (block, template) pairs, not correlations:

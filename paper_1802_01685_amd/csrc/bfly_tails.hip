@@ -7,12 +7,13 @@
 // and scaled by 1/sqrt(E) of the window around each sample), sum_tau (h . z_tau)^2 equals
 // sum_l R_h(l) R_z(l) over the lags |l| < L, R the autocorrelations, which by Parseval is
 // sum_f |H(f)|^2 Q(f) / N with Q the cosine transform of R_z.  The search pass then keeps
-// every (tau, k) with |rho| above kappa * margin * sigma_pred as a candidate while it sums
-// the exact rho^2; afterwards the exact thresholds kappa * sigma_k select the tails among
-// the candidates.  That is exact whenever no exact threshold lies below its predicted one
-// and the candidates fit: k_tails_check verifies both per series and flags a series for
-// which either fails, and the ordinary tails pass then runs for it.  Either way the tails,
-// sigma and counts are those of the two-pass search, bit for bit.
+// every (tau, k) with |rho| above kappa * margin * sigma_pred as a candidate (the FFT form:
+// every (block, k) pair holding one) while it sums the exact rho^2; afterwards the exact
+// thresholds kappa * sigma_k select the tails among the candidates (the FFT form transforms
+// the listed pairs again).  That is exact whenever no exact threshold lies below its
+// predicted one and the candidates fit: k_tails_check verifies both per series and flags a
+// series for which either fails, and the ordinary tails pass then runs for it.  Either way
+// the tails, sigma and counts are those of the two-pass search, bit for bit.
 #include "bfly_internal.h"
 
 #include <hip/hip_runtime.h>
