@@ -290,3 +290,63 @@ def test_coincidence_errors(bf):
         with pytest.raises(bf.BflyError) as e:
             bf.coincidence(bank, t[0], t[1], 400 - p.L + 1, dtau, df)
         assert e.value.status == bf.BF_EINVAL
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fft", "f16f6"])
+def test_tails_light_curve_share_sampled_templates(bf, prec, monkeypatch):
+    """The tail search at full size, as the benchmark runs it: one GPU's 720,000-template
+    share (L = 2000) against the 64 s light curve and its control at kappa = 5.  The FP64
+    oracle forms rho at every offset for 16 seeded templates of each series (its sigma needs
+    them all; 8 templates with GPU tails, 8 at random): their sigma and their tails are
+    checked with the band rule of check_tails.
+    The single pass is also held to the two-pass search bit for bit on the whole output."""
+    from synth import light_curve_series
+    p = bank_params("light_curve_share")
+    xs = [light_curve_series(), light_curve_series(control=True)]
+    kappa = 5.0
+    bank = bf.bank_create(p, prec)
+    outs1, t1 = _search_tails(bf, bank, xs, kappa, 1 << 20)
+    outs2, t2 = _tails_run(bf, bank, xs, kappa, {"BF_TAILS_TWO_PASS": "1"}, monkeypatch)
+    del bank
+    torch.cuda.empty_cache()
+    for i in range(2):
+        for key in outs2[i]:
+            assert np.array_equal(outs1[i][key].view(np.uint8), outs2[i][key].view(np.uint8)), \
+                (i, key)
+        for key in ("sigma", "tau", "k", "rho", "counts"):
+            assert np.array_equal(np.asarray(t1[i][key]).view(np.uint8),
+                                  np.asarray(t2[i][key]).view(np.uint8)), (i, key)
+        assert t1[i]["n"] == t2[i]["n"] and t1[i]["n"] <= (1 << 20)
+    grid = O.grid(p)
+    K = grid.f0.shape[0]
+    tol = TOL[prec]
+    floor = 1.0 / np.sqrt(p.L)
+    rng = np.random.default_rng(77)
+    for i, (x32, g) in enumerate(zip(xs, t1)):
+        x = x32.astype(np.float64)
+        # 8 templates that have GPU tails and 8 at random
+        with_tails = np.unique(g["k"] - int(grid.k_global[0]))
+        ks = np.unique(np.concatenate([rng.choice(with_tails, min(8, with_tails.shape[0]),
+                                                  replace=False),
+                                       rng.choice(K, 8, replace=False)]))
+        H = O.templates(p.fs, p.L, grid.f0[ks], grid.fdot[ks])
+        r, degen = O.rho(x, H)                           # [W, 16], FP64
+        ok = ~degen
+        s64 = np.sqrt((r[ok] ** 2).sum(axis=0) / ok.sum())
+        rel = np.abs(g["sigma"][ks].astype(np.float64) - s64) / s64
+        assert rel.max() <= tol, f"series {i}: sigma rel error {rel.max():.3e}"
+        thr = kappa * s64
+        for j, k in enumerate(ks):
+            kg = int(grid.k_global[k])
+            mine = g["tau"][g["k"] == kg]
+            a = np.abs(r[:, j])
+            band = 2 * tol * np.maximum(np.maximum(a, thr[j]), floor)
+            clear = np.nonzero(a > thr[j] + band)[0]
+            assert np.isin(clear, mine).all(), f"series {i} k {kg}: clear FP64 tails missing"
+            assert np.all(a[mine] > thr[j] - band[mine]), f"series {i} k {kg}: GPU tail below"
+            rg = g["rho"][g["k"] == kg].astype(np.float64)
+            err = np.abs(rg - r[mine, j]) / np.maximum(np.abs(r[mine, j]), floor)
+            assert err.max(initial=0.0) <= tol, f"series {i} k {kg}: tail rho error"
+        print(f"light-curve share {prec} series {i}: {g['n']} tails, sigma rel err "
+              f"{rel.max():.2e}, sampled templates' tails {sum(int((g['k'] == int(grid.k_global[k])).sum()) for k in ks)}")
