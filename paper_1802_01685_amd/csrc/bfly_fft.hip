@@ -1554,6 +1554,14 @@ hipError_t launch_fft_pass(const BatchHdr* hdr, int64_t blocks, const BankDev& b
   BFLY_FFT_DISPATCH(launch_fft_pass_t, hdr, blocks, b, p, s);
 }
 
+int contraction_wgs_per_cu(const BankDev& b) {
+  if (b.precision != P_FFT) return 1;
+  if (b.fft_m == 4096 && fft4k_enabled()) return 2;        // k_fft4k: 2 x 4 waves
+  const int waves = 4 * fft_occupancy();                    // k_fft_main: waves per CU
+  const int wg_waves = std::max(1, b.fft_m / 512);          // M / 8 threads per work-group
+  return std::max(1, waves / std::max(1, wg_waves));
+}
+
 hipError_t launch_pred(const BatchHdr* hdr, int32_t seg_slots, const GridDev& g,
                        const BankDev& b, float kappa, float margin, hipStream_t s) {
   (void)seg_slots;

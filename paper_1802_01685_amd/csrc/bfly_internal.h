@@ -265,6 +265,9 @@ int pred_points(const BankDev& b);
 // c_tau holds the block and c_k the template, and launch_fft_pairs extracts the tails of the
 // listed pairs of every series whose check passed.
 bool fft_onepass_available(const BankDev& b);
+// Work-groups of the bank's contraction kernel that are resident on one CU (the grid of a
+// persistent launch is the CU count times this).
+int contraction_wgs_per_cu(const BankDev& b);
 hipError_t launch_fft_pairs(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
                             hipStream_t s);
 hipError_t launch_acf(const BatchHdr* hdr, int32_t seg_slots, int L, hipStream_t s);

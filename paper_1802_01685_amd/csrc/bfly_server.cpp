@@ -394,8 +394,9 @@ bf_status bf_server_create(const bf_bank* bank, const bf_server_desc* desc, bf_s
         return hip_error(e, "server stream/table setup");
       }
       std::memset(t.table_pin, 0, tb);
-      // Capture: table upload + the five kernels, grids sized for max_slots series and one
-      // work-group per CU for the contraction kernel (it loops over the tick's items).
+      // Capture: table upload + the five kernels, grids sized for max_slots series and as
+      // many contraction work-groups as the CUs hold at once (they loop over the tick's
+      // items).
       if ((e = hipStreamBeginCapture(t.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
         free_server(s);
         return hip_error(e, "hipStreamBeginCapture");
@@ -404,7 +405,9 @@ bf_status bf_server_create(const bf_bank* bank, const bf_server_desc* desc, bf_s
                                      t.stream);
       bf_status kst = ce == hipSuccess
                           ? enqueue_kernels(bank->dev, s->sp, t.table_dev, desc->max_slots,
-                                            s->x_blocks, s->slots, t.stream, nullptr)
+                                            s->x_blocks,
+                                            (int64_t)s->slots * contraction_wgs_per_cu(bank->dev),
+                                            t.stream, nullptr)
                           : hip_error(ce, "hipMemcpyAsync(capture)");
       e = hipStreamEndCapture(t.stream, &t.graph);
       if (kst != BF_OK || e != hipSuccess) {
