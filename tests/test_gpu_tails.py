@@ -350,3 +350,48 @@ def test_tails_light_curve_share_sampled_templates(bf, prec, monkeypatch):
             assert err.max(initial=0.0) <= tol, f"series {i} k {kg}: tail rho error"
         print(f"light-curve share {prec} series {i}: {g['n']} tails, sigma rel err "
               f"{rel.max():.2e}, sampled templates' tails {sum(int((g['k'] == int(grid.k_global[k])).sum()) for k in ks)}")
+
+
+def test_fft_tails_with_many_templates_per_bin(bf):
+    """An FFT bank whose f0 bin holds 65,535 templates: the single pass keeps each bin's
+    argmax as a 16-bit offset, so such a bank takes the two-pass route (its rho^2 sums by
+    atomics).  sigma and the tails of 16 sampled templates against FP64 rho at every offset,
+    and the search outputs equal those of a plain search."""
+    from synth import chirp_samples
+    p = BankParams(fs=1024.0, L=1024, n_f0=1, n_fdot=65535, f0_min=60.0, f0_max=60.0,
+                   fdot_min=-200.0, fdot_max=200.0)
+    gr = O.grid(p)
+    sig, _ = chirp_samples(20000, p.fs, 9000 / p.fs, gr.f0[40000], gr.fdot[40000])
+    x = (white_noise(20000, 61) + 0.5 * sig).astype(np.float32)
+    bank = bf.bank_create(p, "fft")
+    kappa = 4.0
+    outs, tails = _search_tails(bf, bank, [x], kappa, 1 << 20)
+    plain = to_np(bf.search_segment(bank, torch.from_numpy(x).cuda(), bf.make_params()))
+    torch.cuda.synchronize()
+    del bank
+    for key in plain:
+        assert np.array_equal(plain[key].view(np.uint8), outs[0][key].view(np.uint8)), key
+    g = tails[0]
+    assert g["n"] > 0 and g["n"] <= (1 << 20)
+    tol = TOL["fft"]
+    floor = 1.0 / np.sqrt(p.L)
+    rng = np.random.default_rng(62)
+    with_tails = np.unique(g["k"] - int(gr.k_global[0]))
+    ks = np.unique(np.concatenate([rng.choice(with_tails, min(8, with_tails.shape[0]),
+                                              replace=False), [40000],
+                                   rng.choice(gr.f0.shape[0], 8, replace=False)]))
+    H = O.templates(p.fs, p.L, gr.f0[ks], gr.fdot[ks])
+    r, degen = O.rho(x.astype(np.float64), H)
+    ok = ~degen
+    s64 = np.sqrt((r[ok] ** 2).sum(axis=0) / ok.sum())
+    rel = np.abs(g["sigma"][ks].astype(np.float64) - s64) / s64
+    assert rel.max() <= tol, f"sigma rel error {rel.max():.3e}"
+    for j, k in enumerate(ks):
+        kg = int(gr.k_global[k])
+        mine = g["tau"][g["k"] == kg]
+        a = np.abs(r[:, j])
+        thr = kappa * s64[j]
+        band = 2 * tol * np.maximum(np.maximum(a, thr), floor)
+        assert np.isin(np.nonzero(a > thr + band)[0], mine).all(), f"k {kg}: FP64 tails missing"
+        assert np.all(a[mine] > thr - band[mine]), f"k {kg}: GPU tail below the threshold"
+    print(f"65,535 templates per bin: {g['n']} tails, sigma rel err {rel.max():.2e}")
