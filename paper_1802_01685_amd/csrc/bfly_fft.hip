@@ -847,19 +847,27 @@ struct SigOut {
 // sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
 // correlation above the kept bound; a flagged (block, template) pair is appended to the
 // series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
+// A store through a global (not generic) pointer: a generic store also counts on the LDS
+// counter, so the LDS reads issued after it would wait for the store to reach memory.
+template <typename T>
+__device__ __forceinline__ void global_store(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 template <int MODE>
 __device__ __forceinline__ void store_sig(const SigOut& so, const unsigned long long (&slot)[4],
                                           int64_t blk, int k, int64_t k_pad) {
   constexpr unsigned long long FLAG = 1ull << 63;
   const unsigned long long s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3];
-  so.part[blk * k_pad + k] = ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG));
+  global_store(so.part + blk * k_pad + k,
+               ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG)));
   if constexpr (MODE == MODE_ONEPASS) {
     if ((s0 | s1 | s2 | s3) & FLAG) {
       const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
       const unsigned long long at = atomicAdd(so.n_cand + shard, 1ull);
       if ((int64_t)at < so.per) {
-        so.c_blk[shard * so.per + (int64_t)at] = (int32_t)blk;
-        so.c_k[shard * so.per + (int64_t)at] = k;
+        global_store(so.c_blk + shard * so.per + (int64_t)at, (int32_t)blk);
+        global_store(so.c_k + shard * so.per + (int64_t)at, k);
       }
     }
   }
