@@ -241,7 +241,7 @@ bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_
  * the contraction: before it, sigma_k is predicted from the series' own spectrum by
  * Parseval's theorem (Sec. 2.2: the mean square of template k's output is the sum over
  * frequency of |H_k|^2 times the power of the locally normalised series); the pass sums the
- * exact rho^2 per template and keeps every (tau, k) above 0.9 kappa times the prediction.
+ * exact rho^2 per template and keeps every (tau, k) above 0.95 kappa times the prediction.
  * A check then selects the tails against the exact kappa * sigma_k; a series whose exact
  * threshold falls below the kept bound, or whose candidate lists overflow, gets a second
  * pass that extracts its tails directly.  Results are the same bit for bit as with two

@@ -854,6 +854,15 @@ __device__ __forceinline__ void global_store(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// The lane's index in its wave, formed where it is used: the volatile keeps the compiler
+// from hoisting it out of a loop, where it (or an address made from it) would hold a
+// register across the whole loop or be spilled and reloaded.
+__device__ __forceinline__ int lane_here() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0" : "=v"(l));
+  return l;
+}
+
 template <int MODE>
 __device__ __forceinline__ void store_sig(const SigOut& so, const unsigned long long (&slot)[4],
                                           int64_t blk, int k, int64_t k_pad) {
@@ -1058,10 +1067,12 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         mirror_pair(ha[r], xa[r], hb[r], xb[r],
                     LEAN ? twiddle16_q<true>(wt, r) : wpair[LEAN ? 0 : r], v0[r], v1[7 - r]);
       if (helper) {
+        // the helpers are lanes 0..3 of wave 0, so t is their lane index
+        const int h = lane_here();
         float2 ya, yb;
-        mirror_pair(hha, hand_x[2 * t], hhb, hand_x[2 * t + 1], whelp, ya, yb);
-        hand[t] = ya;
-        hand[7 - t] = yb;
+        mirror_pair(hha, hand_x[2 * h], hhb, hand_x[2 * h + 1], whelp, ya, yb);
+        hand[h] = ya;
+        hand[7 - h] = yb;
       }
       if constexpr (MODE == MODE_ONEPASS)
         tlo_next = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
