@@ -273,6 +273,25 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return (lane_u64(v, 15) + lane_u64(v, 31)) + (lane_u64(v, 47) + lane_u64(v, 63));
 }
 
+// The sum of a float over the wave in a fixed order (pairs, quads, half rows, rows, then the
+// four rows), the same in every lane: a + b = b + a exactly, so the partners of each step
+// hold equal values.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  v += dpp_f32<0x140>(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 15));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 47));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  return (r0 + r1) + (r2 + r3);
+}
+
 // One template sample in float64, with the same formula as the direct bank:
 // cos(2 pi frac(f0 t + fdot t^2 / 2)), t = n / fs.
 __device__ __forceinline__ double template_sample(double fs, double f0, double fdot, int n) {
@@ -854,6 +873,27 @@ __device__ __forceinline__ void global_store(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// Running maximum with its argument kept in one 16-bit half of a register: where |v| > m,
+// m = |v| and half HI of arg = the low half of rel (the other half is kept).  Three
+// instructions: the compare, the select of m, and a select whose sub-dword operands and
+// destination (SDWA) replace only the chosen half.  A comparison with a NaN is false, as in
+// the plain C form (a = |v|; if (a > m) { m = a; arg.half = rel; }).
+template <int HI>
+__device__ __forceinline__ void max_arg16(float v, float& m, unsigned& arg, unsigned rel) {
+  if constexpr (HI)
+    asm("v_cmp_gt_f32_e64 vcc, |%2|, %0\n\t"
+        "v_cndmask_b32_e64 %0, %0, |%2|, vcc\n\t"
+        "v_cndmask_b32_sdwa %1, %1, %3, vcc dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE "
+        "src0_sel:WORD_1 src1_sel:WORD_0"
+        : "+v"(m), "+v"(arg) : "v"(v), "v"(rel) : "vcc");
+  else
+    asm("v_cmp_gt_f32_e64 vcc, |%2|, %0\n\t"
+        "v_cndmask_b32_e64 %0, %0, |%2|, vcc\n\t"
+        "v_cndmask_b32_sdwa %1, %1, %3, vcc dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE "
+        "src0_sel:WORD_0 src1_sel:WORD_0"
+        : "+v"(m), "+v"(arg) : "v"(v), "v"(rel) : "vcc");
+}
+
 // The lane's index in its wave, formed where it is used: the volatile keeps the compiler
 // from hoisting it out of a loop, where it (or an address made from it) would hold a
 // register across the whole loop or be spilled and reloaded.
@@ -1148,20 +1188,19 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
           q = fmaf(rr, rr, q);
           if constexpr (MODE == MODE_ONEPASS) {
             mr = fmaxf(mr, fabsf(rr));
-            // the running maximum of the search (below), in the same sweep
-            const float a = fabsf(v);
-            const bool g = a > binmax[o];
-            // the low (even o) or high (odd o) half of the register becomes rel1: one byte
-            // permutation of {cur, rel1} (bytes 0-3 of rel1, 4-7 of cur)
+            // the running maximum of the search (below), in the same sweep; the low (even o)
+            // or high (odd o) half of the register takes rel1 where |v| is a new maximum
             const unsigned rel1 = (unsigned)(k - bin * nfd + 1);
-            const unsigned cur = barg2[o >> 1];
-            const unsigned nv = __builtin_amdgcn_perm(cur, rel1, (o & 1) ? 0x01000504u : 0x07060100u);
-            barg2[o >> 1] = g ? nv : cur;
-            binmax[o] = g ? a : binmax[o];
+            if (o & 1)
+              max_arg16<1>(v, binmax[o], barg2[o >> 1], rel1);
+            else
+              max_arg16<0>(v, binmax[o], barg2[o >> 1], rel1);
           }
         }
-        unsigned long long f = (unsigned long long)__double2ll_rn((double)q * SIGMA_FIX_SCALE);
-        f = wave_sum_u64(f);
+        // the wave's float sum in a fixed order, then fixed point (order-independent across
+        // waves, blocks and the atomic route)
+        unsigned long long f =
+            (unsigned long long)__double2ll_rn((double)wave_sum_f32(q) * SIGMA_FIX_SCALE);
         // single pass: bit 63 of the wave's slot (free: the sums stay below 2^63) flags a
         // correlation above the kept bound in this wave
         if constexpr (MODE == MODE_ONEPASS)
