@@ -233,7 +233,7 @@ typedef struct {
  * sums and thresholds (K_pad * 16 bytes), the candidate lists of the single pass (12 bytes a
  * candidate, K_pad * W / 16384 of them clamped to [2^16, 2^24]), the locally normalised
  * series and its lag sums (n * 4 + (17 L + 1) * 8 bytes), the predictor's spectrum and,
- * with an FFT bank, per-block rho^2 partial sums (tiles * K_pad * 8 bytes). */
+ * with an FFT bank, rho^2 partial sums per block and wave (tiles * 4 * K_pad * 8 bytes). */
 bf_status bf_tails_workspace_bytes(const bf_bank* bank, const int64_t* n, int32_t n_segs,
                                    const bf_search_params* params, size_t* bytes);
 

@@ -426,7 +426,7 @@ size_t series_ws_bytes(const BankDev& b, int64_t n, bool tails) {
     off = align256(off + (size_t)(b.L + 1) * sizeof(double));
     off = align256(off + (size_t)(pred_points(b) / 2 + 1) * sizeof(float));
     if (b.precision == P_FFT && b.fft_m == 4096)
-      off = align256(off + (size_t)fft_blocks(b, W) * b.K_pad * sizeof(unsigned long long));
+      off = align256(off + (size_t)fft_blocks(b, W) * 4 * b.K_pad * sizeof(unsigned long long));
   }
   if (b.precision == P_FFT) off = align256(off + fft_blocks(b, W) * (size_t)(b.fft_m + 2) * 8);
   return off;
@@ -481,7 +481,7 @@ void series_ws_carve(const BankDev& b, int64_t n, char* base, SeriesBufs* s, boo
     s->sig_part = nullptr;
     if (b.precision == P_FFT && b.fft_m == 4096) {
       s->sig_part = (unsigned long long*)(base + off);
-      off = align256(off + (size_t)fft_blocks(b, W) * b.K_pad * sizeof(unsigned long long));
+      off = align256(off + (size_t)fft_blocks(b, W) * 4 * b.K_pad * sizeof(unsigned long long));
     }
   }
   s->xspec = nullptr;
@@ -755,6 +755,8 @@ bf_status enqueue_onepass_tail_kernels(const bf_bank* bank, const SearchDev& sp_
   if (te) HIP_TRY(hipEventRecord(te->ev[4], stream), "hipEventRecord");
   HIP_TRY(launch_finalize(table_dev, seg_slots, xb, b, sp_pass, stream), "k_finalize launch");
   HIP_TRY(launch_sigma(table_dev, seg_slots, b, sp_tails, stream), "k_sigma launch");
+  if (b.precision == P_FFT)
+    HIP_TRY(launch_fft_pair_list(table_dev, seg_slots, b, stream), "k_fft_pair_list launch");
   HIP_TRY(launch_tails_check(table_dev, seg_slots, b, stream), "k_tails_check launch");
   // the tails of the series whose check passed: from the kept correlations (direct forms) or
   // by transforming the listed (block, template) pairs again (FFT form)

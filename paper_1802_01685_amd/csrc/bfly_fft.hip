@@ -363,7 +363,6 @@ __global__ __launch_bounds__(Plan<M>::T) void k_fft_bank(GridDev g, BankDev b,
 // thr_lo[k] = kappa * margin * sqrt(P_k / (n_ok N)), P_k = sum over f in [0, N) of
 // |H_k(f)|^2 Q(f) (Q from k_qspec, real and even: the bins 1 .. N/2 - 1 count twice), or +inf
 // past the bank's templates and for a series without a non-degenerate offset.
-constexpr int PRED_SERIES = 8;   // series per sweep of a template's spectrum
 
 __device__ __forceinline__ void pred_store(const SegDesc& sg, int64_t k, const BankDev& b,
                                            double P, int N, float kappa, float margin) {
@@ -373,37 +372,67 @@ __device__ __forceinline__ void pred_store(const SegDesc& sg, int64_t k, const B
   sg.thr_lo[k] = v;
 }
 
-// The FFT form: the spectra are the bank's (N = 2M); one wave per template, every series.
+// The FFT form: the spectra are the bank's (N = 2M); one wave per template, NS series per
+// sweep of its spectrum.  Every load of a sweep is unconditional (a series without Q reads
+// the bank's first row instead, and its sum is dropped), so a lane issues its PRED_U bins'
+// loads of the spectrum and of every Q before it waits for any.
+template <int NS>
 __global__ __launch_bounds__(256) void k_pred_bank(const BatchHdr* __restrict__ hdr, BankDev b,
                                                    float kappa, float margin) {
+  typedef const __attribute__((address_space(1))) float* gfloat;
+  constexpr int PRED_U = 5;
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= b.K_pad) return;
   const int M = b.fft_m, N = 2 * b.fft_m;
   const float2* hk = (const float2*)b.data + k * (int64_t)(M + 2);
   const SegDesc* segs = hdr_segs(hdr);
-  for (int s0 = 0; s0 < hdr->n_segs; s0 += PRED_SERIES) {
-    double P[PRED_SERIES];
+  const int n_segs = hdr->n_segs;
+  for (int s0 = 0; s0 < n_segs; s0 += NS) {
+    gfloat qs[NS];
+    bool use[NS];
 #pragma unroll
-    for (int i = 0; i < PRED_SERIES; ++i) P[i] = 0.0;
-    for (int f = lane; f <= M; f += 64) {
-      const float2 h = k < b.K ? hk[f] : make_float2(0.0f, 0.0f);
-      const double w = (f == 0 || f == M) ? 1.0 : 2.0;
-      const double h2 = w * ((double)h.x * h.x + (double)h.y * h.y);
+    for (int i = 0; i < NS; ++i) {
+      const float* q = s0 + i < n_segs ? segs[s0 + i].qspec : nullptr;
+      use[i] = q && segs[s0 + i].thr_lo;
+      qs[i] = (gfloat)(q ? q : (const float*)b.data);
+    }
+    double P[NS];
 #pragma unroll
-      for (int i = 0; i < PRED_SERIES; ++i)
-        if (s0 + i < hdr->n_segs && segs[s0 + i].qspec) P[i] += h2 * (double)segs[s0 + i].qspec[f];
+    for (int i = 0; i < NS; ++i) P[i] = 0.0;
+    for (int f0 = lane; f0 <= M; f0 += 64 * PRED_U) {
+      float2 h[PRED_U];
+      float qv[PRED_U][NS];
+#pragma unroll
+      for (int u = 0; u < PRED_U; ++u) {
+        const int f = f0 + 64 * u;
+        // bins past M read bin M and get weight 0 below; the spectra hold K_pad rows (the
+        // sums of rows past K are dropped)
+        const int fc = f <= M ? f : M;
+        h[u] = hk[fc];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) qv[u][i] = qs[i][fc];
+      }
+#pragma unroll
+      for (int u = 0; u < PRED_U; ++u) {
+        const int f = f0 + 64 * u;
+        const double w = f > M ? 0.0 : (f == 0 || f == M) ? 1.0 : 2.0;
+        const double h2 = w * ((double)h[u].x * h[u].x + (double)h[u].y * h[u].y);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) P[i] += h2 * (double)qv[u][i];
+      }
     }
 #pragma unroll
-    for (int i = 0; i < PRED_SERIES; ++i) {
+    for (int i = 0; i < NS; ++i) {
       double v = P[i];
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0 && s0 + i < hdr->n_segs && segs[s0 + i].thr_lo)
-        pred_store(segs[s0 + i], k, b, v, N, kappa, margin);
+      if (lane == 0 && use[i]) pred_store(segs[s0 + i], k, b, v, N, kappa, margin);
     }
   }
 }
+
+constexpr int PRED_SERIES = 8;   // series per sweep of a template's spectrum
 
 // The direct forms: one work-group per template builds it as the FFT bank does (float64,
 // rounded to float32), transforms it on N = 2M points, and sums |H|^2 Q for every series.
@@ -851,21 +880,6 @@ __device__ __forceinline__ void pass8x2(const float2* __restrict__ src, float2* 
   }
 }
 
-// Where thread 0 of k_fft4k puts a template's sums: the series' pointers, read once per work
-// item so that no scalar load is in flight during the template loop (a scalar load returns
-// out of order, which makes every LDS wait of a pass wait for all of its reads).
-struct SigOut {
-  unsigned long long* part;   // [blocks][K_pad] rho^2 partial sums
-  unsigned long long* n_cand; // [CAND_SHARDS] pair counters (single pass)
-  int32_t* c_blk;             // listed pairs: block
-  int32_t* c_k;               //               template
-  int64_t per;                // pairs per shard
-};
-
-// Thread 0 of k_fft4k: template k's rho^2 sum over the work-group's block (the four wave
-// sums) into the block's partial-sum row.  In the single pass bit 63 of a wave's sum flags a
-// correlation above the kept bound; a flagged (block, template) pair is appended to the
-// series' pair list (shard = work-group index mod 256, as the direct forms' candidates).
 // A store through a global (not generic) pointer: a generic store also counts on the LDS
 // counter, so the LDS reads issued after it would wait for the store to reach memory.
 template <typename T>
@@ -903,25 +917,6 @@ __device__ __forceinline__ int lane_here() {
   return l;
 }
 
-template <int MODE>
-__device__ __forceinline__ void store_sig(const SigOut& so, const unsigned long long (&slot)[4],
-                                          int64_t blk, int k, int64_t k_pad) {
-  constexpr unsigned long long FLAG = 1ull << 63;
-  const unsigned long long s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3];
-  global_store(so.part + blk * k_pad + k,
-               ((s0 & ~FLAG) + (s1 & ~FLAG)) + ((s2 & ~FLAG) + (s3 & ~FLAG)));
-  if constexpr (MODE == MODE_ONEPASS) {
-    if ((s0 | s1 | s2 | s3) & FLAG) {
-      const int shard = (int)(blockIdx.x & (CAND_SHARDS - 1));
-      const unsigned long long at = atomicAdd(so.n_cand + shard, 1ull);
-      if ((int64_t)at < so.per) {
-        global_store(so.c_blk + shard * so.per + (int64_t)at, (int32_t)blk);
-        global_store(so.c_k + shard * so.per + (int64_t)at, k);
-      }
-    }
-  }
-}
-
 template <int SMAX, int MODE>
 __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ hdr, BankDev b,
                                                   SearchDev p) {
@@ -935,9 +930,6 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
   // j mod NS = m: entry [(r - 1) NS + m] (lanes read consecutive entries)
   __shared__ float2 tab2[7 * 8];
   __shared__ float2 tab3[7 * 64];
-  // sigma and single-pass modes: each wave's fixed-point sum of rho^2 for the last two
-  // templates (by parity); thread 0 adds the four after the next barrier and stores it
-  __shared__ unsigned long long sig_slot[2][4];
   const SegDesc* segs = hdr_segs(hdr);
   const float2* spectra = (const float2*)b.data;
   const int n_ranges = hdr->n_ranges;
@@ -1081,9 +1073,13 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
       hhb = row_load(hr, 8u * (unsigned)(M - ha_idx), 0u);
     };
     load_h(k_lo);
-    [[maybe_unused]] SigOut so;
+    // sigma and single-pass modes: this block's four rows of per-wave rho^2 sums, read once
+    // per work item (no scalar load in flight during the template loop: one returns out of
+    // order, which makes every LDS wait of a pass wait for all of its reads)
+    [[maybe_unused]] unsigned long long* sig_row = nullptr;
     if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS)
-      so = SigOut{sg.sig_part, sg.n_cand, sg.c_tau, sg.c_k, sg.cand_cap / CAND_SHARDS};
+      if (sg.sig_part)
+        sig_row = sg.sig_part + (blk * 4 + __builtin_amdgcn_readfirstlane(t >> 6)) * b.K_pad;
     // the single pass's kept bounds: a vector load one template ahead, on the same counter
     // as the spectrum prefetch (a scalar load would be waited for with the LDS reads)
     [[maybe_unused]] __amdgpu_buffer_rsrc_t thr_r;
@@ -1149,13 +1145,6 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         pass8x2<64, false, S2, S3>(bufq, bufp, w, w, y0, y1);
       }
       __syncthreads();
-      if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
-        // the previous template's four wave sums were written before this template's first
-        // barrier and are overwritten only after the next template's third; by now the
-        // prefetch of the next template's spectrum has landed, so the store's wait is short
-        if (t == 0 && k > k_lo && so.part)
-          store_sig<MODE>(so, sig_slot[(k - 1) & 1], blk, k - 1, b.K_pad);
-      }
       if constexpr (LEAN) {
         // pass 4's twiddle powers as running products of the bases
         float2 wa[7], wb[7];
@@ -1201,13 +1190,14 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         // waves, blocks and the atomic route)
         unsigned long long f =
             (unsigned long long)__double2ll_rn((double)wave_sum_f32(q) * SIGMA_FIX_SCALE);
-        // single pass: bit 63 of the wave's slot (free: the sums stay below 2^63) flags a
+        // single pass: bit 63 of the wave's sum (free: the sums stay below 2^63) flags a
         // correlation above the kept bound in this wave
         if constexpr (MODE == MODE_ONEPASS)
-          if (__any(mr > tlo)) f |= 1ull << 63;
+          if (__any(mr > tlo)) f |= SIG_FLAG;
+        // each wave stores its own sum (no cross-wave step, so no wave waits for another)
         if ((t & 63) == 0) {
-          if (so.part)
-            sig_slot[k & 1][__builtin_amdgcn_readfirstlane(t >> 6)] = f;
+          if (sig_row)
+            global_store(sig_row + k, f);
           else if (f != 0ull)
             atomicAdd(sg.sig_acc + k, f);
         }
@@ -1285,12 +1275,6 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
         ++bin;
         left = nfd;
       }
-    }
-    if constexpr (MODE == MODE_SIGMA || MODE == MODE_ONEPASS) {
-      // the item's last template
-      __syncthreads();
-      if (t == 0 && k_hi > k_lo && so.part)
-        store_sig<MODE>(so, sig_slot[(k_hi - 1) & 1], blk, k_hi - 1, b.K_pad);
     }
   }
 }
@@ -1486,6 +1470,61 @@ bool fft_onepass_available(const BankDev& b) {
   return b.fft_m == 4096 && fft4k_enabled() && b.n_fdot < 65535;
 }
 
+namespace {
+
+// The single pass's list of (block, template) pairs holding a correlation above the kept
+// bound: the pairs with the flag bit in any of their four wave sums.  Shard s takes the
+// 64-template groups g with g mod 256 = s, block by block, so a shard's pairs come in runs
+// of one block (k_fft4k_pairs reloads a block's spectrum only when the block changes), the
+// shards share the flagged templates evenly wherever they cluster, and the list is the same
+// on every run.  A shard's count may exceed its capacity (k_tails_check then flags the
+// series).  One work-group per (shard, series).
+__global__ __launch_bounds__(256) void k_fft_pair_list(const BatchHdr* __restrict__ hdr,
+                                                       BankDev b) {
+  if ((int)blockIdx.y >= hdr->n_segs) return;
+  const SegDesc& sg = hdr_segs(hdr)[blockIdx.y];
+  if (!sg.redo || !sg.sig_part || !sg.n_cand || !sg.c_tau) return;
+  __shared__ unsigned int cnt[4];
+  const int shard = (int)blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t per = sg.cand_cap / CAND_SHARDS;
+  const int64_t n_groups = b.K_pad / 64;
+  int64_t n = 0;
+  for (int64_t blk = 0; blk < sg.n_tiles; ++blk) {
+    const unsigned long long* rows = sg.sig_part + blk * 4 * b.K_pad;
+    for (int64_t g0 = shard; g0 < n_groups; g0 += 4 * CAND_SHARDS) {
+      const int64_t g = g0 + (int64_t)w * CAND_SHARDS;
+      const int64_t k = g * 64 + lane;
+      bool fl = false;
+      if (g < n_groups)
+        fl = ((rows[k] | rows[b.K_pad + k] | rows[2 * b.K_pad + k] | rows[3 * b.K_pad + k]) &
+              SIG_FLAG) != 0ull;
+      const unsigned long long bal = __ballot(fl);
+      if (lane == 0) cnt[w] = (unsigned int)__popcll(bal);
+      __syncthreads();
+      int64_t at = n;
+      for (int i = 0; i < w; ++i) at += cnt[i];
+      at += __popcll(bal & ((1ull << lane) - 1ull));
+      if (fl && at < per) {
+        sg.c_tau[shard * per + at] = (int32_t)blk;
+        sg.c_k[shard * per + at] = (int32_t)k;
+      }
+      n += (int64_t)cnt[0] + cnt[1] + cnt[2] + cnt[3];
+      __syncthreads();
+    }
+  }
+  if (t == 0) sg.n_cand[shard] = (unsigned long long)n;
+}
+
+}  // namespace
+
+hipError_t launch_fft_pair_list(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_fft_pair_list, dim3(CAND_SHARDS, (unsigned)seg_slots), dim3(256), 0, s,
+                     hdr, b);
+  return hipGetLastError();
+}
+
 hipError_t launch_fft_pairs(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
                             hipStream_t s) {
   const unsigned grid = (unsigned)std::min<int64_t>((int64_t)seg_slots * CAND_SHARDS, 512);
@@ -1622,10 +1661,16 @@ int contraction_wgs_per_cu(const BankDev& b) {
 
 hipError_t launch_pred(const BatchHdr* hdr, int32_t seg_slots, const GridDev& g,
                        const BankDev& b, float kappa, float margin, hipStream_t s) {
-  (void)seg_slots;
   if (b.precision == P_FFT) {
-    hipLaunchKernelGGL(k_pred_bank, dim3((unsigned)((b.K_pad + 3) / 4)), dim3(256), 0, s, hdr,
-                       b, kappa, margin);
+    const dim3 grid((unsigned)((b.K_pad + 3) / 4));
+    if (seg_slots <= 1)
+      hipLaunchKernelGGL(k_pred_bank<1>, grid, dim3(256), 0, s, hdr, b, kappa, margin);
+    else if (seg_slots <= 2)
+      hipLaunchKernelGGL(k_pred_bank<2>, grid, dim3(256), 0, s, hdr, b, kappa, margin);
+    else if (seg_slots <= 4)
+      hipLaunchKernelGGL(k_pred_bank<4>, grid, dim3(256), 0, s, hdr, b, kappa, margin);
+    else
+      hipLaunchKernelGGL(k_pred_bank<8>, grid, dim3(256), 0, s, hdr, b, kappa, margin);
     return hipGetLastError();
   }
   const unsigned blocks = (unsigned)b.K_pad;

@@ -30,6 +30,9 @@ constexpr int MAX_HIST_BINS = 4096;
 // (< 2^31) stays below 2^63 and a u64 accumulator cannot wrap.
 constexpr double SPEC_FIX_SCALE = 2147483648.0;     // 2^31
 constexpr double SIGMA_FIX_SCALE = 2147483648.0;    // 2^31
+// The FFT form's single pass marks a wave's rho^2 sum with bit 63 (the sums stay below 2^63)
+// when one of its correlations is above the kept bound.
+constexpr unsigned long long SIG_FLAG = 1ull << 63;
 constexpr int64_t MAX_SERIES_SAMPLES = (int64_t)1 << 31;
 static_assert((double)MAX_SERIES_SAMPLES * 1.001 * SPEC_FIX_SCALE < 9223372036854775808.0,
               "spectrum sums cannot wrap");
@@ -91,9 +94,9 @@ struct SegDesc {
   float2* xspec;        // FFT form: [n_tiles][M + 2] spectra of the data blocks
   // kappa-sigma tails (null unless the search extracts them)
   unsigned long long* sig_acc;   // [K_pad] fixed-point sums of rho^2 per template
-  unsigned long long* sig_part;  // FFT form at N = 8192: [n_tiles][K_pad] the same sums per
-                                 // block (one plain store per work item and template, no
-                                 // atomics contending across work-groups; summed by k_sigma)
+  unsigned long long* sig_part;  // FFT form at N = 8192: [n_tiles][4][K_pad] the same sums
+                                 // per block and wave (one plain store per wave and template,
+                                 // no atomics; summed by k_sigma), bit 63 = SIG_FLAG
   unsigned long long* n_ok;      // [1] non-degenerate offsets
   float* thr;                    // [K_pad] kappa * sigma_k (+inf past K)
   float* sigma;                  // [K] output sigma_k
@@ -264,13 +267,16 @@ hipError_t launch_fft_search(const BatchHdr* hdr, int64_t blocks, const BankDev&
 // transforms its listed pairs again; the tails pass then runs only for flagged series.
 int pred_points(const BankDev& b);
 // The FFT form's search kernel has the single-pass mode (N = 8192, fewer than 2^16
-// templates per f0 bin).  Its candidates are (block, template) pairs, not correlations:
-// c_tau holds the block and c_k the template, and launch_fft_pairs extracts the tails of the
-// listed pairs of every series whose check passed.
+// templates per f0 bin).  Its candidates are (block, template) pairs, not correlations: the
+// pass flags them in its per-wave rho^2 sums, launch_fft_pair_list lists them per shard (c_tau
+// holds the block and c_k the template, n_cand the count), and launch_fft_pairs extracts the
+// tails of the listed pairs of every series whose check passed.
 bool fft_onepass_available(const BankDev& b);
 // Work-groups of the bank's contraction kernel that are resident on one CU (the grid of a
 // persistent launch is the CU count times this).
 int contraction_wgs_per_cu(const BankDev& b);
+hipError_t launch_fft_pair_list(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
+                                hipStream_t s);
 hipError_t launch_fft_pairs(const BatchHdr* hdr, int32_t seg_slots, const BankDev& b,
                             hipStream_t s);
 hipError_t launch_acf(const BatchHdr* hdr, int32_t seg_slots, int L, hipStream_t s);

@@ -1726,8 +1726,8 @@ __global__ __launch_bounds__(256) void k_sigma(const BatchHdr* __restrict__ hdr,
     float thr = __builtin_inff();
     if (k < b.K) {
       unsigned long long acc = 0ull;
-      if (sg.sig_part)
-        for (int64_t blk = 0; blk < sg.n_tiles; ++blk) acc += sg.sig_part[blk * b.K_pad + k];
+      if (sg.sig_part)   // FFT form: per block and wave, with the single pass's flag bit
+        for (int64_t r = 0; r < 4 * sg.n_tiles; ++r) acc += sg.sig_part[r * b.K_pad + k] & ~SIG_FLAG;
       else
         acc = sg.sig_acc[k];
       const double sd = nok > 0.0 ? sqrt((double)acc / SIGMA_FIX_SCALE / nok) : 0.0;
