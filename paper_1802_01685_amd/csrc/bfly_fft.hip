@@ -1283,9 +1283,11 @@ __global__ __launch_bounds__(256, 2) void k_fft4k(const BatchHdr* __restrict__ h
 // series whose check passed (redo = 0; a flagged series gets the full tails pass instead).
 // Per pair the transform of k_fft4k with the same operations in the same order, so rho is
 // the same bit for bit, then the compare against kappa sigma_k.  Work unit = (series, shard
-// of the pair list); a work-group takes a shard's pairs one after another.
+// of the pair list); a work-group takes a shard's pairs one after another.  Two work-groups
+// per CU: within 256 registers only the block change (a few times per shard) reloads spilled
+// values.
 template <int SMAX>
-__global__ __launch_bounds__(256, 1) void k_fft4k_pairs(const BatchHdr* __restrict__ hdr,
+__global__ __launch_bounds__(256, 2) void k_fft4k_pairs(const BatchHdr* __restrict__ hdr,
                                                         BankDev b) {
   using namespace fft4k;
   constexpr int NO = 2 * SMAX;
