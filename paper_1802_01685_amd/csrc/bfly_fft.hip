@@ -787,7 +787,12 @@ __global__ __launch_bounds__(Plan<M>::T, OCC) void k_fft_main(const BatchHdr* __
 //   per-offset packed maxima with one atomic max each.  That is the same merge as the other
 //   forms (value first, then the lower template), so the results do not depend on how the
 //   bank is split into bins and ranges.
-// The sigma and tails modes are those of k_fft_main.
+// The sigma and tails modes are those of k_fft_main.  The single-pass mode also forms rho in
+// the same sweep as the maxima: per template each wave sums rho^2 over its lanes' outputs
+// (float32 in a fixed order, then fixed point), marks the sum (bit 63) when one of its
+// correlations is above the template's kept bound, and stores it to its own row of the
+// series' partial sums; the bin's argmax is kept as 16-bit template offsets, two to a
+// register, to stay within 256 registers.
 namespace fft4k {
 constexpr int M = 4096;
 constexpr int PADN = M + M / 8;   // the largest stage layout (SH = 3)
