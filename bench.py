@@ -183,13 +183,12 @@ def time_form(bf, torch, p, xs, prec, steps, warmup, keep_offsets=None, t_block=
 
 
 def fft_points(L):
-    """The real FFT length the library picks for L (least transform work per valid output)."""
-    m, best = 512, 1e300
-    for mm, lg in ((512, 9), (1024, 10), (2048, 11), (4096, 12)):
-        v = 2 * mm - L + 1
-        if v >= 1 and mm * lg / v < best * 0.999:
-            m, best = mm, mm * lg / v
-    return m
+    """The complex transform length M (real FFT length N = 2M) the library uses: 4096 for
+    every template length (BF_FFT_POINTS = N picks a shorter one)."""
+    v = os.environ.get("BF_FFT_POINTS")
+    if v in ("1024", "2048", "4096") and int(v) - L + 1 >= 1:
+        return int(v) // 2
+    return 4096
 
 
 def roofline(res, p, prec, tile):

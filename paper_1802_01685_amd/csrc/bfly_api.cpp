@@ -113,18 +113,17 @@ void fill_geometry(const bf_bank_desc* d, GridDev* g, BankDev* b) {
   b->precision = d->precision;
   b->fft_m = 0;
   if (d->precision == BF_FFT) {
-    // real FFT length N = 2M, M in 512..4096: the one with the least transform work per
-    // valid output, M log2 M / (2M - L + 1) (e.g. N = 8192 for L = 2000 or 4096, 4096 for
-    // L = 512)
-    double best = 1e300;
-    for (int32_t m = 512, lg = 9; m <= 4096; m *= 2, ++lg) {
-      const int32_t valid = 2 * m - d->L + 1;
-      if (valid < 1) continue;
-      const double cost = (double)m * lg / (double)valid;
-      if (cost < best * 0.999) {
-        best = cost;
-        b->fft_m = m;
-      }
+    // real FFT length N = 2M = 8192 for every L (<= 4096): its kernel (k_fft4k) runs at 1.5
+    // to 2.6 times the flop rate of the general one (k_fft_main at N = 4096 and 2048), which
+    // outweighs the up to 8% less transform work per valid output, M log2 M / (2M - L + 1),
+    // that a shorter transform has for short templates.  BF_FFT_POINTS = 1024, 2048 or 4096
+    // selects a shorter transform on the general kernel (a comparison knob, read at each
+    // bank description; ignored where 2M - L + 1 < 1).
+    b->fft_m = 4096;
+    const char* e = getenv("BF_FFT_POINTS");
+    if (e && *e) {
+      const long v = strtol(e, nullptr, 10);
+      if ((v == 1024 || v == 2048 || v == 4096) && v - d->L + 1 >= 1) b->fft_m = (int32_t)(v / 2);
     }
   }
 }

@@ -56,6 +56,20 @@ def test_bank_bytes_and_validation_on_host(lib):
     # N = 8192 for L = 4096
     df = lib.make_desc(bank_params("strain"), "fft")
     assert lib.bank_bytes(df) == 65536 * (4096 + 2) * 8 + 256
+    # N = 8192 for every template length; BF_FFT_POINTS = N picks a shorter transform where
+    # it holds a template (the small strain-like bank: 256 templates of L = 512)
+    ds = lib.make_desc(bank_params("small_strain"), "fft")
+    assert lib.bank_bytes(ds) == 256 * (4096 + 2) * 8 + 256
+    import os
+    try:
+        os.environ["BF_FFT_POINTS"] = "2048"
+        assert lib.bank_bytes(ds) == 256 * (1024 + 2) * 8 + 256
+        os.environ["BF_FFT_POINTS"] = "1024"
+        assert lib.bank_bytes(ds) == 256 * (512 + 2) * 8 + 256
+        os.environ["BF_FFT_POINTS"] = "1024"
+        assert lib.bank_bytes(df) == 65536 * (4096 + 2) * 8 + 256   # L = 4096: too short
+    finally:
+        os.environ.pop("BF_FFT_POINTS", None)
     df.L = 4097
     with pytest.raises(lib.BflyError):
         lib.bank_bytes(df)

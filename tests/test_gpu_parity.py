@@ -322,3 +322,27 @@ def test_search_on_a_side_stream(bf):
         for k in ref:
             assert np.array_equal(ref[k].view(np.uint8), got[k].view(np.uint8)), k
         del junk, out
+
+
+@pytest.mark.parametrize("points", [1024, 2048, 4096])
+def test_fft_shorter_transforms(bf, points, monkeypatch):
+    """The FFT form's general kernel, selected by BF_FFT_POINTS = N < 8192 (the library uses
+    N = 8192 for every template length): the L = 512 small strain-like bank at every offset,
+    and the ragged 48-tap shape with degenerate windows, against the FP64 oracle."""
+    monkeypatch.setenv("BF_FFT_POINTS", str(points))
+    p = bank_params("small_strain")
+    x32 = small_strain_series().astype(np.float32)
+    x64 = x32.astype(np.float64)
+    g, bank = _run(bf, p, x32, "fft")
+    assert bf.bank_bytes(bf.make_desc(p, "fft")) == 256 * (points // 2 + 2) * 8 + 256
+    orc = O.search(x64, p)
+    st = check_against_oracle(x64, p, g, orc, "fft", f"small_strain/N={points}")
+    assert np.allclose(g["spectrum"], orc["spectrum"], rtol=TOL["fft"], atol=0)
+    pr, n, norm, t_block, _ = SMALL["ragged"]
+    xr = _edge_series(n, 7, pr.L)
+    gr, _ = _run(bf, pr, xr, "fft", t_block=t_block, norm=norm, hist_bins=64)
+    orr = O.search(xr.astype(np.float64), pr, norm=norm, hist_bins=64)
+    st2 = check_against_oracle(xr.astype(np.float64), pr, gr, orr, "fft", f"ragged/N={points}",
+                               norm=norm)
+    assert st2["n_degenerate"] > 0
+    print(f"N = {points}: {st}; ragged {st2}")

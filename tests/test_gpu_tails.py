@@ -395,3 +395,24 @@ def test_fft_tails_with_many_templates_per_bin(bf):
         assert np.isin(np.nonzero(a > thr + band)[0], mine).all(), f"k {kg}: FP64 tails missing"
         assert np.all(a[mine] > thr - band[mine]), f"k {kg}: GPU tail below the threshold"
     print(f"65,535 templates per bin: {g['n']} tails, sigma rel err {rel.max():.2e}")
+
+
+@pytest.mark.parametrize("points", [2048, 4096])
+def test_fft_tails_shorter_transforms(bf, points, monkeypatch):
+    """The FFT form's three-pass tail search on the general kernel (BF_FFT_POINTS = N < 8192):
+    the L = 512 small strain-like bank with a chirp at kappa = 4, every offset against FP64;
+    the search outputs of the tail search equal a plain search bit for bit."""
+    monkeypatch.setenv("BF_FFT_POINTS", str(points))
+    p = bank_params("small_strain")
+    x32 = small_strain_series().astype(np.float32)
+    bank = bf.bank_create(p, "fft")
+    outs, tails = _search_tails(bf, bank, [x32], 4.0, 1 << 18)
+    orc = O.sigma_tails(x32.astype(np.float64), p, 4.0)
+    st = check_tails(x32.astype(np.float64), p, tails[0], orc, 4.0, TOL["fft"],
+                     f"small_strain/N={points}")
+    assert st["n_fp64"] > 0
+    plain = to_np(bf.search_segment(bank, torch.from_numpy(x32).cuda(), bf.make_params()))
+    torch.cuda.synchronize()
+    for key in plain:
+        assert np.array_equal(plain[key].view(np.uint8), outs[0][key].view(np.uint8)), key
+    print(points, st)
