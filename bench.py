@@ -434,6 +434,28 @@ def serving_leg(bf, prec, n_segments, budget_gib, slots):
             "capacity_segments_per_s": capacity, "ticks": stats["ticks"]}
 
 
+def length_sweep(bf, torch, lengths=(256, 512, 1024, 2048, 4096),
+                 forms=("fft", "f16f6", "fp8", "fp32")):
+    """Correlations/s by template length: 65,536 templates (256 f0 x 256 fdot, fs = L so the
+    chirps stay 1 s long) against 131,072 samples of seeded white noise, 1 untimed and 3 timed
+    steps per (L, form)."""
+    import numpy as np
+    from synth import BankParams, white_noise
+    x = torch.from_numpy(white_noise(131072, seed=7).astype(np.float32)).cuda()
+    rows = []
+    for L in lengths:
+        fs = float(L)
+        p = BankParams(fs=fs, L=L, n_f0=256, n_fdot=256, f0_min=fs / 50, f0_max=fs / 4,
+                       fdot_min=-fs / 4, fdot_max=fs / 4)
+        for prec in forms:
+            r = time_form(bf, torch, p, [x], prec, steps=3, warmup=1)
+            rows.append({"L": L, "form": prec, "ms_per_step": round(r["ms_per_step"], 3),
+                         "correlations_per_s": r["value"], "correlations_per_step": r["corr_per_step"],
+                         "fft_points": 2 * fft_points(L) if prec == "fft" else None})
+            log(f"L = {L} {prec}: {r['value']:.3g} corr/s")
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -458,6 +480,9 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a known-size reference "
                          "for hardware byte counters)")
+    ap.add_argument("--length-sweep", action="store_true",
+                    help="instead of the benchmark: the FFT form against the direct forms by "
+                         "template length (one JSON line)")
     ap.add_argument("--oracle-worker", nargs=2, metavar=("N", "OUT"), help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -472,7 +497,8 @@ def main() -> int:
     t_start = time.perf_counter()
 
     # the oracle child starts before this process touches the GPU
-    oracle = start_oracle(args.cpu_offsets) if args.cpu_offsets > 0 else None
+    oracle = (start_oracle(args.cpu_offsets)
+              if args.cpu_offsets > 0 and not args.length_sweep else None)
 
     import numpy as np
     import torch
@@ -483,6 +509,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     bf.lib()
+    if args.length_sweep:
+        print(json.dumps({"length_sweep": length_sweep(bf, torch)}), flush=True)
+        return 0
     p = bank_params("light_curve_share")
     x = light_curve_series()
     xc = light_curve_series(control=True)
