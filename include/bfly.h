@@ -70,8 +70,10 @@ typedef enum {
                     scale; h_hi*x + h_lo*x (two MFMA products per tap).  The data's fp16
                     rounding (2^-11) bounds the error: 2.4e-3 of the noise scale */
   BF_FFT = 4,    /* FFT correlation (Sec. 2.2): float32 template spectra, overlap-save with
-                    real FFTs of length N = 2M, M in 512..4096 minimising M log2 M per valid
-                    output (N - L + 1); L <= 4096; the same outputs as the direct forms.
+                    real FFTs of length N = 8192 (N - L + 1 valid outputs per block; the
+                    environment variable BF_FFT_POINTS = 1024, 2048 or 4096 selects a shorter
+                    transform that holds the template, on the general kernel); L <= 4096;
+                    the same outputs as the direct forms.
                     Bound 1e-5, growing as 3.2e-6 x (RMS of the loudest transform block
                     near the window / the window's RMS) where that ratio exceeds ~3 */
   BF_F16F8 = 5,  /* fp16 product of the fp16-rounded template and data, plus the two residual
