@@ -1503,7 +1503,9 @@ __global__ __launch_bounds__(256) void k_fft_pair_list(const BatchHdr* __restric
       const int64_t g = g0 + (int64_t)w * CAND_SHARDS;
       const int64_t k = g * 64 + lane;
       bool fl = false;
-      if (g < n_groups)
+      // the pass writes the sums of the bank's templates only (k < K); the padding rows'
+      // words are whatever the workspace held
+      if (g < n_groups && k < b.K)
         fl = ((rows[k] | rows[b.K_pad + k] | rows[2 * b.K_pad + k] | rows[3 * b.K_pad + k]) &
               SIG_FLAG) != 0ull;
       const unsigned long long bal = __ballot(fl);

@@ -416,3 +416,33 @@ def test_fft_tails_shorter_transforms(bf, points, monkeypatch):
     for key in plain:
         assert np.array_equal(plain[key].view(np.uint8), outs[0][key].view(np.uint8)), key
     print(points, st)
+
+
+@pytest.mark.parametrize("prec", ["fft", "f16f6", "fp32"])
+def test_tails_any_workspace_contents(bf, prec):
+    """The tail search does not depend on what its workspace held before: a workspace of all
+    one bits (every stale word flagged, every stale count huge) and one of zeros give the
+    same search outputs, sigma, tails and counts bit for bit.  A 5 x 7 bank leaves 29
+    padding templates in its 64-template granule."""
+    p = BankParams(fs=1024.0, L=1024, n_f0=5, n_fdot=7, f0_min=40.0, f0_max=300.0,
+                   fdot_min=-150.0, fdot_max=150.0)
+    xs = [torch.from_numpy(white_noise(20000, 51).astype(np.float32)).cuda(),
+          torch.from_numpy(white_noise(15000, 52).astype(np.float32)).cuda()]
+    bank = bf.bank_create(p, "fft" if prec == "fft" else prec)
+    prm = bf.make_params()
+    nbytes = bf.tails_workspace_bytes(bank, [int(x.shape[0]) for x in xs], prm)
+    res = []
+    for fill in (0x00, 0xFF):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda")
+        outs, tails = bf.search_tails(bank, xs, 3.0, 1 << 16, prm, workspace=ws)
+        torch.cuda.synchronize()
+        res.append(([to_np(o) for o in outs], [_tails_np(t) for t in tails]))
+    (o0, t0), (o1, t1) = res
+    assert all(t["n"] > 0 for t in t0)
+    for i in range(2):
+        for key in o0[i]:
+            assert np.array_equal(o0[i][key].view(np.uint8), o1[i][key].view(np.uint8)), (i, key)
+        for key in ("sigma", "tau", "k", "rho", "counts"):
+            assert np.array_equal(np.asarray(t0[i][key]).view(np.uint8),
+                                  np.asarray(t1[i][key]).view(np.uint8)), (i, key)
+        assert t0[i]["n"] == t1[i]["n"]
